@@ -1,0 +1,202 @@
+/*
+ * tflbm.h -- C ABI of the MI355X (gfx950) thin-film lattice Boltzmann library.
+ *
+ * The library advances the D2Q9 film-height populations of the thin-film
+ * lattice Boltzmann method of Zitz, Scagliarini, Maddu, Darhuber and Harting,
+ * "A lattice Boltzmann method for thin liquid film hydrodynamics"
+ * (arXiv:1810.07642), Sec. II, on a periodic nx x ny lattice (Sec. III):
+ *
+ *   f_l(x + c_l, t + 1) = f_l + omega (f_l^eq - f_l) + 3 w_l c_l . F_tot     (eq. "LBE")
+ *   f^eq: shallow-water equilibrium with hydrostatic term g h^2/2            (eq. "equilibria")
+ *   F_tot = -h grad p_film - nu alpha_delta(h) u + h (ax, ay)                (eqs. "force", "forcefric")
+ *   p_film = -gamma (lap h + kappa(x) [(h_* / h)^n - (h_* / h)^m])                (eqs. "pfilm", "disjoiningP")
+ *   kappa(x) = (1 - cos theta(x)) (n - 1)(m - 1) / ((n - m) h_*)
+ *   alpha_delta(h) = 6 h / (2 h^2 + 6 delta h + 3 delta^2)                     (eq. "alphafric")
+ *   grad, lap: isotropic D2Q9 stencils                                         (eqs. "derivative", "n_laplace")
+ *   h = sum_l f_l, h u = sum_l c_l f_l, nu = (tau - 1/2)/3, omega = 1/tau.
+ *
+ * Readings of the printed equations (denominators of the equilibrium taken
+ * with lattice speed 1, the Laplacian without the printed weights, the
+ * disjoining sign that gives partial wetting) are those of the FP64 oracle
+ * the library is tested against.
+ *
+ * Conventions common to every call:
+ *  - All arrays passed in or out are row-major [ny][nx], x fastest, FP64,
+ *    dense (row pitch nx), in HIP device memory unless a pointer is named h_*.
+ *  - The library never allocates device memory.  The caller allocates the
+ *    workspace (tflbm_workspace_bytes), the adjoint workspace
+ *    (tflbm_adj_bytes), checkpoints (tflbm_state_bytes) and captures
+ *    (tflbm_capture_bytes), keeps them alive until the stream work that uses
+ *    them has completed, and frees them.  The handle owns host memory only.
+ *  - Calls marked (async) enqueue work on `stream` and return at once;
+ *    errors of already-launched kernels surface at the next blocking call.
+ *    Calls marked (blocking) synchronise `stream`.
+ *  - Return value: TFLBM_OK (0) or a negative TFLBM_E* code.  No exceptions
+ *    and no abort cross the ABI.  A handle is not thread-safe: calls on one
+ *    handle must be serialised by the caller.
+ */
+#ifndef TFLBM_H
+#define TFLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *tflbm_stream_t; /* a hipStream_t; NULL = default stream */
+
+enum {
+  TFLBM_OK = 0,
+  TFLBM_EINVAL = -1,     /* bad argument: dimensions, tau <= 1/2, h_* <= 0, null pointer, size */
+  TFLBM_EUNSTABLE = -2,  /* tflbm_check_params only: 2 nu / delta^2 >= 2 (friction recurrence unstable near h -> 0) */
+  TFLBM_EHIP = -3,       /* a HIP runtime error; tflbm_last_error() gives its text */
+  TFLBM_ENONFINITE = -4, /* a step produced h <= 0 or a non-finite h */
+  TFLBM_ESTATE = -5      /* call out of order (e.g. step before init, adjoint step before seed) */
+};
+
+/* Population storage forms.  Arithmetic is FP64 for TFLBM_FP64 and FP32 otherwise.
+ * TFLBM_FP16S stores the rest population f_0 in FP32 and the 8 moving
+ * populations in FP16 as (f_l - E_l(href)) * 2^fp16_scale_log2, where
+ * E_l(h) is the rest equilibrium (g h^2/6 on axes, g h^2/24 on diagonals);
+ * the rest population absorbs the FP16 rounding so that the stored
+ * populations of a site sum to its height. */
+enum { TFLBM_FP64 = 0, TFLBM_FP32 = 1, TFLBM_FP16S = 2 };
+
+typedef struct tflbm_params {
+  int32_t nx, ny;          /* periodic lattice size, >= 1 each, ny * roundup(nx, 64) < 2^31 */
+  int32_t prec;            /* TFLBM_FP64, TFLBM_FP32 or TFLBM_FP16S */
+  int32_t n_exp, m_exp;    /* disjoining exponents n != m, 1..32 (paper: 9 and 3) */
+  int32_t fp16_scale_log2; /* TFLBM_FP16S scale exponent s, 0..24 */
+  double tau;              /* BGK relaxation time, > 1/2 */
+  double gamma;            /* surface tension, >= 0 */
+  double g;                /* gravity in the equilibrium's g h^2/2; < 0 destabilises */
+  double hstar;            /* precursor film thickness h_* > 0 */
+  double delta;            /* slip length, >= 0 */
+  double ax, ay;           /* body acceleration: F = h (ax, ay) */
+  double theta0;           /* uniform contact angle used when tflbm_init gets d_theta == NULL */
+  double fp16_href;        /* TFLBM_FP16S shift height href (>= 0) */
+} tflbm_params;
+
+typedef struct tflbm_sim tflbm_sim; /* opaque; host memory only */
+
+/* Library version string. */
+const char *tflbm_version(void);
+
+/* Text of a TFLBM_E* code. */
+const char *tflbm_strerror(int code);
+
+/* Text of the last HIP error seen by any call on `sim` (or "" if none). */
+const char *tflbm_last_error(const tflbm_sim *sim);
+
+/* Fills *p with the defaults: tau 1, gamma 0.01, g 0, h_* 0.05, (n, m) = (9, 3),
+ * delta 1, no body force, theta0 0, FP64, fp16 scale 2^12, href 0; nx = ny = 0. */
+void tflbm_default_params(tflbm_params *p);
+
+/* Validates *p without creating anything.  TFLBM_OK, TFLBM_EINVAL, or
+ * TFLBM_EUNSTABLE for the warning-class friction bound 2 nu/delta^2 >= 2
+ * (uniform-film velocity recurrence u_{t+1} = u_t (1 - nu alpha/h) needs
+ * nu alpha/h < 2; its supremum over h > 0 is 2 nu/delta^2).  */
+int tflbm_check_params(const tflbm_params *p);
+
+/* Creates a handle for the lattice and parameters in *p (copied).  Performs
+ * the TFLBM_EINVAL checks of tflbm_check_params; a TFLBM_EUNSTABLE warning
+ * does not prevent creation.  *out receives the handle or NULL. */
+int tflbm_create(const tflbm_params *p, tflbm_sim **out);
+
+/* Releases the handle (host memory only; no device memory is owned). */
+void tflbm_destroy(tflbm_sim *sim);
+
+/* Bytes of device workspace the handle needs: two population buffers, the
+ * kappa field, a status word and reduction partials.  Depends only on the
+ * parameters. */
+size_t tflbm_workspace_bytes(const tflbm_sim *sim);
+
+/* Attaches a caller-allocated device workspace of `bytes` >= tflbm_workspace_bytes
+ * bytes, 256-byte aligned.  Re-binding detaches the previous one and clears
+ * the initialised state. */
+int tflbm_bind(tflbm_sim *sim, void *d_ws, size_t bytes);
+
+/* (async) Initial populations f_l = f_l^eq(h0, u = 0) (the equilibrium at
+ * rest) and kappa from theta (Sec. II, eq. "disjoiningP").  d_h0: [ny][nx]
+ * FP64, every value > 0 (checked on the device; reported by tflbm_check).
+ * d_theta: [ny][nx] FP64 contact angles, or NULL for the uniform
+ * params.theta0 (then the step reads no kappa field).  Sets the step count
+ * to 0 and clears the status word. */
+int tflbm_init(tflbm_sim *sim, const double *d_h0, const double *d_theta, tflbm_stream_t stream);
+
+/* (async) Advances nsteps >= 0 time steps of eq. "LBE". */
+int tflbm_step(tflbm_sim *sim, int64_t nsteps, tflbm_stream_t stream);
+
+/* Number of steps taken since tflbm_init (host counter). */
+int64_t tflbm_step_count(const tflbm_sim *sim);
+
+/* (async) Height h = sum_l f_l and velocity u = (sum_l c_l f_l)/h of the
+ * current populations, computed in FP64 from the stored values.  Each output
+ * is [ny][nx] FP64 device memory; any of them may be NULL to skip it. */
+int tflbm_read(const tflbm_sim *sim, double *d_h, double *d_ux, double *d_uy, tflbm_stream_t stream);
+
+/* (blocking) Total mass sum_{x,l} f_l(x) in FP64 (deterministic two-pass
+ * reduction) into *h_mass (host memory).  The method conserves it exactly in
+ * real arithmetic (Sec. III B). */
+int tflbm_mass(const tflbm_sim *sim, double *h_mass, tflbm_stream_t stream);
+
+/* (blocking) TFLBM_OK, or TFLBM_ENONFINITE if a step since tflbm_init met
+ * h <= 0 or a non-finite h at an updated site, or if h0 had such a value. */
+int tflbm_check(const tflbm_sim *sim, tflbm_stream_t stream);
+
+/* Bytes of one population buffer (a checkpoint of the state). */
+size_t tflbm_state_bytes(const tflbm_sim *sim);
+
+/* (async) Copies the current populations into d_dst (tflbm_state_bytes bytes). */
+int tflbm_state_save(const tflbm_sim *sim, void *d_dst, tflbm_stream_t stream);
+
+/* (async) Replaces the current populations by d_src (written by
+ * tflbm_state_save of a handle with the same parameters) and sets the step
+ * counter to `step`.  The kappa field is kept. */
+int tflbm_state_load(tflbm_sim *sim, const void *d_src, int64_t step, tflbm_stream_t stream);
+
+/* ---- Reverse mode (the vector-Jacobian product of the step) ------------
+ * The adjoint of n steps from f = E(h0) with respect to h0 and theta, for a
+ * loss whose gradient with respect to the final height is given.  Use:
+ *   seed with dL/dh_N; then for each step t = N-1 ... 0, in that order, call
+ *   tflbm_adj_step with the capture of step t (the moments at the start of
+ *   step t, written by tflbm_step_capture); then tflbm_adj_finish.
+ * The adjoint state is stored in the working precision (FP64 for
+ * TFLBM_FP64, FP32 otherwise); the kappa gradient accumulates in FP64. */
+
+/* Bytes of one step's capture: h, h u_x, h u_y at the start of the step. */
+size_t tflbm_capture_bytes(const tflbm_sim *sim);
+
+/* (async) Like tflbm_step, and also writes the capture of step i
+ * (0 <= i < nsteps) to d_capture + i * tflbm_capture_bytes. */
+int tflbm_step_capture(tflbm_sim *sim, int64_t nsteps, void *d_capture, tflbm_stream_t stream);
+
+/* Bytes of the adjoint workspace: two adjoint population buffers and the
+ * FP64 kappa-gradient field. */
+size_t tflbm_adj_bytes(const tflbm_sim *sim);
+
+/* (async) Starts a reverse pass in d_adj (tflbm_adj_bytes bytes, 256-byte
+ * aligned): the adjoint of the final populations is dL/dh_N(x) for every l,
+ * and the kappa gradient is zeroed.  d_grad_h: [ny][nx] FP64. */
+int tflbm_adj_seed(tflbm_sim *sim, void *d_adj, const double *d_grad_h, tflbm_stream_t stream);
+
+/* (async) Moves the adjoint from the end of step t to its start, using the
+ * capture of step t (d_capture_t, tflbm_capture_bytes bytes), and adds the
+ * step's contribution to the kappa gradient. */
+int tflbm_adj_step(tflbm_sim *sim, void *d_adj, const void *d_capture_t, tflbm_stream_t stream);
+
+/* (async) dL/dh0 = sum_l lambda_l dE_l/dh0 and dL/dtheta = dL/dkappa dkappa/dtheta.
+ * d_h0: the initial height used by tflbm_init; d_theta: its theta field, or
+ * NULL if tflbm_init was given NULL (then *d_grad_theta still receives the
+ * per-site gradient with respect to a theta field equal to theta0).
+ * Outputs [ny][nx] FP64; either may be NULL. */
+int tflbm_adj_finish(tflbm_sim *sim, const void *d_adj, const double *d_h0, const double *d_theta,
+                     double *d_grad_h0, double *d_grad_theta, tflbm_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFLBM_H */

@@ -1,0 +1,283 @@
+// C ABI of the thin-film lattice Boltzmann library: parameter validation,
+// workspace layout, launch orchestration and error codes (forward part).
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "launch.h"
+#include "sim.h"
+
+using namespace tflbm;
+
+namespace tflbm {
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int hip_status(const tflbm_sim *s, hipError_t e) {
+  if (e == hipSuccess) return TFLBM_OK;
+  if (s) s->last_error = hipGetErrorString(e);
+  return TFLBM_EHIP;
+}
+
+int choose_rows(int ny, int nstrips, const char *env_name) {
+  if (const char *e = std::getenv(env_name)) {
+    const int r = std::atoi(e);
+    if (r > 0) return r < ny ? r : ny;
+  }
+  // aim at ~2048 marching wavefronts (8 per CU) with chunks of 16..128 rows
+  const int want_chunks = (2048 + nstrips - 1) / nstrips;
+  int rows = (ny + want_chunks - 1) / want_chunks;
+  if (rows < 16) rows = 16;
+  if (rows > 128) rows = 128;
+  if (rows > ny) rows = ny;
+  return rows;
+}
+
+StepArgs make_step_args(const tflbm_sim *s) {
+  StepArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.src = s->ws + (s->cur == 0 ? s->off_a : s->off_b);
+  A.dst = s->ws + (s->cur == 0 ? s->off_b : s->off_a);
+  A.kfield = s->kfield ? (const void *)(s->ws + s->off_k) : nullptr;
+  A.capture = nullptr;
+  A.flag = (int *)(s->ws + s->off_flag);
+  A.nx = s->p.nx;
+  A.ny = s->p.ny;
+  A.ldx = s->ldx;
+  A.plane = s->plane;
+  A.nstrips = s->nstrips;
+  A.H = s->rows;
+  A.ntiles = s->ntiles;
+  A.per_xcd = s->per_xcd;
+  A.n_exp = s->p.n_exp;
+  A.m_exp = s->p.m_exp;
+  A.omega = 1.0 / s->p.tau;
+  A.gamma = s->p.gamma;
+  A.nu = (s->p.tau - 0.5) / 3.0;
+  A.hstar = s->p.hstar;
+  A.delta = s->p.delta;
+  A.ax = s->p.ax;
+  A.ay = s->p.ay;
+  A.g = s->p.g;
+  A.kappa0 = s->kappa0;
+  const double gh2 = s->p.g * s->p.fp16_href * s->p.fp16_href;
+  A.shift[0] = 0.0;
+  for (int l = 1; l < 9; ++l) A.shift[l] = (l & 1) ? gh2 / 6.0 : gh2 / 24.0;
+  A.qscale = std::ldexp(1.0f, s->p.fp16_scale_log2);
+  A.qinv = std::ldexp(1.0f, -s->p.fp16_scale_log2);
+  return A;
+}
+
+}  // namespace tflbm
+
+extern "C" {
+
+const char *tflbm_version(void) { return "tflbm 0.1 (gfx950)"; }
+
+const char *tflbm_strerror(int code) {
+  switch (code) {
+    case TFLBM_OK: return "ok";
+    case TFLBM_EINVAL: return "invalid argument";
+    case TFLBM_EUNSTABLE: return "parameters outside the stable range of the friction recurrence (2 nu/delta^2 >= 2)";
+    case TFLBM_EHIP: return "HIP runtime error";
+    case TFLBM_ENONFINITE: return "non-finite or non-positive film height";
+    case TFLBM_ESTATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+const char *tflbm_last_error(const tflbm_sim *sim) { return sim ? sim->last_error.c_str() : ""; }
+
+void tflbm_default_params(tflbm_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->prec = TFLBM_FP64;
+  p->n_exp = 9;
+  p->m_exp = 3;
+  p->fp16_scale_log2 = 12;
+  p->tau = 1.0;
+  p->gamma = 0.01;
+  p->g = 0.0;
+  p->hstar = 0.05;
+  p->delta = 1.0;
+  p->theta0 = 0.0;
+  p->fp16_href = 0.0;
+}
+
+static bool is_fin(double v) { return std::isfinite(v); }
+
+int tflbm_check_params(const tflbm_params *p) {
+  if (!p) return TFLBM_EINVAL;
+  if (p->nx < 1 || p->ny < 1) return TFLBM_EINVAL;
+  const int64_t ldx = ((int64_t)p->nx + 63) / 64 * 64;
+  if ((int64_t)p->ny * ldx >= ((int64_t)1 << 31)) return TFLBM_EINVAL;
+  if (p->prec < TFLBM_FP64 || p->prec > TFLBM_FP16S) return TFLBM_EINVAL;
+  if (p->n_exp < 1 || p->n_exp > 32 || p->m_exp < 1 || p->m_exp > 32 || p->n_exp == p->m_exp) return TFLBM_EINVAL;
+  if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24) return TFLBM_EINVAL;
+  if (!is_fin(p->tau) || !(p->tau > 0.5)) return TFLBM_EINVAL;
+  if (!is_fin(p->gamma) || p->gamma < 0) return TFLBM_EINVAL;
+  if (!is_fin(p->g) || !is_fin(p->ax) || !is_fin(p->ay) || !is_fin(p->theta0)) return TFLBM_EINVAL;
+  if (!is_fin(p->hstar) || !(p->hstar > 0)) return TFLBM_EINVAL;
+  if (!is_fin(p->delta) || p->delta < 0) return TFLBM_EINVAL;
+  if (!is_fin(p->fp16_href) || p->fp16_href < 0) return TFLBM_EINVAL;
+  const double nu = (p->tau - 0.5) / 3.0;
+  if (p->delta == 0.0 || 2.0 * nu / (p->delta * p->delta) >= 2.0) return TFLBM_EUNSTABLE;
+  return TFLBM_OK;
+}
+
+int tflbm_create(const tflbm_params *p, tflbm_sim **out) {
+  if (!out) return TFLBM_EINVAL;
+  *out = nullptr;
+  const int chk = tflbm_check_params(p);
+  if (chk == TFLBM_EINVAL) return chk;
+  tflbm_sim *s = new (std::nothrow) tflbm_sim();
+  if (!s) return TFLBM_EINVAL;
+  s->p = *p;
+  s->ldx = (p->nx + 63) / 64 * 64;
+  s->plane = (int64_t)p->ny * s->ldx;
+  const size_t P = (size_t)s->plane;
+  s->pop_bytes = p->prec == TFLBM_FP64 ? 72 * P : (p->prec == TFLBM_FP32 ? 36 * P : 20 * P);
+  s->kf_bytes = (size_t)work_bytes(p->prec) * P;
+  s->n_partials = 1024;
+  size_t o = 0;
+  s->off_a = o; o = align_up(o + s->pop_bytes, 4096);
+  s->off_b = o; o = align_up(o + s->pop_bytes, 4096);
+  s->off_k = o; o = align_up(o + s->kf_bytes, 4096);
+  s->off_flag = o; o = align_up(o + 256, 256);
+  s->off_part = o; o = align_up(o + 8 * (size_t)s->n_partials, 256);
+  s->off_out = o; o = align_up(o + 256, 4096);
+  s->ws_bytes = o;
+  s->kconst = (double)((p->n_exp - 1) * (p->m_exp - 1)) / ((double)(p->n_exp - p->m_exp) * p->hstar);
+  s->kappa0 = (1.0 - std::cos(p->theta0)) * s->kconst;
+  const int outw = step_columns_per_strip(p->prec);
+  s->nstrips = (p->nx + outw - 1) / outw;
+  s->rows = choose_rows(p->ny, s->nstrips, "TFLBM_ROWS");
+  s->ntiles = s->nstrips * ((p->ny + s->rows - 1) / s->rows);
+  s->per_xcd = (s->ntiles + 7) / 8;
+  const int aw = adj_columns_per_strip();
+  s->adj_nstrips = (p->nx + aw - 1) / aw;
+  s->adj_rows = choose_rows(p->ny, s->adj_nstrips, "TFLBM_ADJ_ROWS");
+  s->adj_ntiles = s->adj_nstrips * ((p->ny + s->adj_rows - 1) / s->adj_rows);
+  s->adj_per_xcd = (s->adj_ntiles + 7) / 8;
+  *out = s;
+  return TFLBM_OK;
+}
+
+void tflbm_destroy(tflbm_sim *sim) { delete sim; }
+
+size_t tflbm_workspace_bytes(const tflbm_sim *sim) { return sim ? sim->ws_bytes : 0; }
+
+int tflbm_bind(tflbm_sim *sim, void *d_ws, size_t bytes) {
+  if (!sim || !d_ws || bytes < sim->ws_bytes || ((uintptr_t)d_ws & 255) != 0) return TFLBM_EINVAL;
+  sim->ws = (char *)d_ws;
+  sim->initialised = false;
+  sim->adj_seeded = false;
+  sim->cur = 0;
+  sim->steps = 0;
+  return TFLBM_OK;
+}
+
+int tflbm_init(tflbm_sim *sim, const double *d_h0, const double *d_theta, tflbm_stream_t stream) {
+  if (!sim || !d_h0) return TFLBM_EINVAL;
+  if (!sim->ws) return TFLBM_ESTATE;
+  hipStream_t st = (hipStream_t)stream;
+  sim->cur = 1;  // init writes into the "dst" of a cur=1 state, i.e. buffer A
+  sim->kfield = d_theta != nullptr;
+  StepArgs A = make_step_args(sim);
+  int rc = hip_status(sim, hipMemsetAsync(sim->ws + sim->off_flag, 0, 256, st));
+  if (rc) return rc;
+  rc = hip_status(sim, launch_init(sim->p.prec, A, d_h0, d_theta, sim->kconst, st));
+  if (rc) return rc;
+  sim->cur = 0;
+  sim->steps = 0;
+  sim->initialised = true;
+  sim->adj_seeded = false;
+  return TFLBM_OK;
+}
+
+static int run_steps(tflbm_sim *sim, int64_t nsteps, void *d_capture, tflbm_stream_t stream) {
+  if (!sim || nsteps < 0) return TFLBM_EINVAL;
+  if (!sim->initialised) return TFLBM_ESTATE;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t cap_bytes = tflbm_capture_bytes(sim);
+  for (int64_t i = 0; i < nsteps; ++i) {
+    StepArgs A = make_step_args(sim);
+    A.capture = d_capture ? (char *)d_capture + (size_t)i * cap_bytes : nullptr;
+    const int rc = hip_status(sim, launch_step(sim->p.prec, A, sim->kfield, d_capture != nullptr, st));
+    if (rc) return rc;
+    sim->cur ^= 1;
+    sim->steps += 1;
+  }
+  return TFLBM_OK;
+}
+
+int tflbm_step(tflbm_sim *sim, int64_t nsteps, tflbm_stream_t stream) {
+  return run_steps(sim, nsteps, nullptr, stream);
+}
+
+int tflbm_step_capture(tflbm_sim *sim, int64_t nsteps, void *d_capture, tflbm_stream_t stream) {
+  if (!d_capture) return TFLBM_EINVAL;
+  return run_steps(sim, nsteps, d_capture, stream);
+}
+
+int64_t tflbm_step_count(const tflbm_sim *sim) { return sim ? sim->steps : -1; }
+
+int tflbm_read(const tflbm_sim *sim, double *d_h, double *d_ux, double *d_uy, tflbm_stream_t stream) {
+  if (!sim) return TFLBM_EINVAL;
+  if (!sim->initialised) return TFLBM_ESTATE;
+  if (!d_h && !d_ux && !d_uy) return TFLBM_OK;
+  StepArgs A = make_step_args(sim);
+  return hip_status(sim, launch_read(sim->p.prec, A, d_h, d_ux, d_uy, (hipStream_t)stream));
+}
+
+int tflbm_mass(const tflbm_sim *sim, double *h_mass, tflbm_stream_t stream) {
+  if (!sim || !h_mass) return TFLBM_EINVAL;
+  if (!sim->initialised) return TFLBM_ESTATE;
+  hipStream_t st = (hipStream_t)stream;
+  StepArgs A = make_step_args(sim);
+  int rc = hip_status(sim, launch_mass(sim->p.prec, A, (double *)(sim->ws + sim->off_part), sim->n_partials,
+                                       (double *)(sim->ws + sim->off_out), st));
+  if (rc) return rc;
+  rc = hip_status(sim, hipMemcpyAsync(h_mass, sim->ws + sim->off_out, sizeof(double), hipMemcpyDeviceToHost, st));
+  if (rc) return rc;
+  return hip_status(sim, hipStreamSynchronize(st));
+}
+
+int tflbm_check(const tflbm_sim *sim, tflbm_stream_t stream) {
+  if (!sim) return TFLBM_EINVAL;
+  if (!sim->initialised) return TFLBM_ESTATE;
+  hipStream_t st = (hipStream_t)stream;
+  int flag = 0;
+  int rc = hip_status(sim, hipMemcpyAsync(&flag, sim->ws + sim->off_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  if (rc) return rc;
+  rc = hip_status(sim, hipStreamSynchronize(st));
+  if (rc) return rc;
+  return flag ? TFLBM_ENONFINITE : TFLBM_OK;
+}
+
+size_t tflbm_state_bytes(const tflbm_sim *sim) { return sim ? sim->pop_bytes : 0; }
+
+int tflbm_state_save(const tflbm_sim *sim, void *d_dst, tflbm_stream_t stream) {
+  if (!sim || !d_dst) return TFLBM_EINVAL;
+  if (!sim->initialised) return TFLBM_ESTATE;
+  const char *src = sim->ws + (sim->cur == 0 ? sim->off_a : sim->off_b);
+  return hip_status(sim, hipMemcpyAsync(d_dst, src, sim->pop_bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+}
+
+int tflbm_state_load(tflbm_sim *sim, const void *d_src, int64_t step, tflbm_stream_t stream) {
+  if (!sim || !d_src || step < 0) return TFLBM_EINVAL;
+  if (!sim->initialised) return TFLBM_ESTATE;
+  char *dst = sim->ws + (sim->cur == 0 ? sim->off_a : sim->off_b);
+  const int rc =
+      hip_status(sim, hipMemcpyAsync(dst, d_src, sim->pop_bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  if (rc) return rc;
+  sim->steps = step;
+  return TFLBM_OK;
+}
+
+size_t tflbm_capture_bytes(const tflbm_sim *sim) {
+  return sim ? 3 * (size_t)sim->plane * work_bytes(sim->p.prec) : 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,27 @@
+// Host-side launchers of the device kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace tflbm {
+
+// Output columns of one marching strip for a storage form.
+int step_columns_per_strip(int prec);
+
+hipError_t launch_step(int prec, const StepArgs &A, bool kfield, bool capture, hipStream_t s);
+hipError_t launch_init(int prec, const StepArgs &A, const double *h0, const double *theta, double kconst,
+                       hipStream_t s);
+hipError_t launch_read(int prec, const StepArgs &A, double *h, double *ux, double *uy, hipStream_t s);
+hipError_t launch_mass(int prec, const StepArgs &A, double *partial, int np, double *out, hipStream_t s);
+
+// Reverse-mode kernels.
+struct AdjArgs;
+hipError_t launch_adj_seed(int prec, const AdjArgs &B, const double *grad_h, hipStream_t s);
+hipError_t launch_adj_step(int prec, const AdjArgs &B, bool kfield, hipStream_t s);
+hipError_t launch_adj_finish(int prec, const AdjArgs &B, const double *h0, const double *theta, double theta0,
+                             double kconst, double *grad_h0, double *grad_theta, hipStream_t s);
+int adj_columns_per_strip();
+
+}  // namespace tflbm

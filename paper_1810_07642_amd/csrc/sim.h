@@ -1,0 +1,47 @@
+// Host-side state behind the opaque tflbm_sim handle (internal).
+#pragma once
+
+#include <string>
+
+#include "../../include/tflbm.h"
+#include "device.h"
+
+struct tflbm_sim {
+  tflbm_params p;
+  int ldx = 0;            // row pitch in elements (nx rounded up to 64)
+  int64_t plane = 0;      // ny * ldx
+  size_t pop_bytes = 0;   // one population buffer
+  size_t kf_bytes = 0;    // kappa field
+  size_t off_a = 0, off_b = 0, off_k = 0, off_flag = 0, off_part = 0, off_out = 0, ws_bytes = 0;
+  int n_partials = 0;
+  char *ws = nullptr;     // bound device workspace
+  bool initialised = false;
+  bool kfield = false;    // kappa read per site (theta field given at init)
+  int cur = 0;            // 0: buffer A holds the current populations
+  int64_t steps = 0;
+  double kconst = 0.0;    // (n - 1)(m - 1)/((n - m) h_*)
+  double kappa0 = 0.0;    // kappa of the uniform theta0
+  // launch shape of the forward step
+  int nstrips = 0, rows = 0, ntiles = 0, per_xcd = 0;
+  // reverse pass
+  int adj_cur = 0;        // 0: first adjoint buffer holds the current adjoint
+  bool adj_seeded = false;
+  int adj_rows = 0, adj_nstrips = 0, adj_ntiles = 0, adj_per_xcd = 0;
+  mutable std::string last_error;
+};
+
+namespace tflbm {
+
+// Bytes per element of the working type.
+inline int work_bytes(int prec) { return prec == kF64 ? 8 : 4; }
+
+// StepArgs for the current state of `s` (src = current, dst = other buffer).
+StepArgs make_step_args(const tflbm_sim *s);
+
+// Records a HIP error on the handle and returns TFLBM_EHIP (or TFLBM_OK).
+int hip_status(const tflbm_sim *s, hipError_t e);
+
+// Rows per chunk of a marching launch with `nstrips` strips over ny rows.
+int choose_rows(int ny, int nstrips, const char *env_name);
+
+}  // namespace tflbm

@@ -1,0 +1,111 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/tflbm.h declares, and validates parameters and call order on the host."""
+import ctypes
+
+import pytest
+
+from paper_1810_07642_amd import _lib
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def params(lib, **kw):
+    p = _lib.Params()
+    lib.tflbm_default_params(ctypes.byref(p))
+    p.nx, p.ny = 64, 48
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_exports_every_declared_function(lib):
+    names = _lib.header_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_version_and_strerror(lib):
+    assert b"gfx950" in lib.tflbm_version()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert len(lib.tflbm_strerror(code)) > 0
+    assert lib.tflbm_strerror(-99) == b"unknown error"
+
+
+def test_struct_layout_matches_header(lib):
+    # six int32 then nine doubles, natural alignment
+    assert ctypes.sizeof(_lib.Params) == 6 * 4 + 9 * 8
+    p = params(lib)
+    assert (p.n_exp, p.m_exp, p.tau, p.gamma, p.hstar, p.delta) == (9, 3, 1.0, 0.01, 0.05, 1.0)
+    assert p.fp16_scale_log2 == 12
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("ny", -3), ("prec", 3), ("tau", 0.5), ("tau", float("nan")), ("hstar", 0.0),
+    ("gamma", -1.0), ("delta", -0.1), ("n_exp", 3), ("m_exp", 0), ("fp16_scale_log2", 30),
+    ("g", float("inf")), ("fp16_href", -1.0),
+])
+def test_invalid_parameters_rejected(lib, field, value):
+    p = params(lib, **{field: value})
+    if field == "n_exp":
+        p.m_exp = 3  # n == m
+    assert lib.tflbm_check_params(ctypes.byref(p)) == _lib.TFLBM_EINVAL
+    h = ctypes.c_void_p(123)
+    assert lib.tflbm_create(ctypes.byref(p), ctypes.byref(h)) == _lib.TFLBM_EINVAL
+    assert not h.value
+
+
+def test_too_large_lattice_rejected(lib):
+    p = params(lib, nx=65536, ny=40000)
+    assert lib.tflbm_check_params(ctypes.byref(p)) == _lib.TFLBM_EINVAL
+
+
+def test_friction_stability_warning(lib):
+    # 2 nu / delta^2 >= 2: nu = 1/6 needs delta > sqrt(1/6) ~ 0.408
+    p = params(lib, delta=0.3)
+    assert lib.tflbm_check_params(ctypes.byref(p)) == _lib.TFLBM_EUNSTABLE
+    h = ctypes.c_void_p()
+    assert lib.tflbm_create(ctypes.byref(p), ctypes.byref(h)) == _lib.TFLBM_OK  # warning only
+    lib.tflbm_destroy(h)
+    assert lib.tflbm_check_params(ctypes.byref(params(lib, delta=0.5))) == _lib.TFLBM_OK
+
+
+@pytest.mark.parametrize("prec,per_site", [(0, 72), (1, 36), (2, 20)])
+def test_workspace_and_state_sizes(lib, prec, per_site):
+    p = params(lib, prec=prec, nx=100, ny=30)
+    h = ctypes.c_void_p()
+    assert lib.tflbm_create(ctypes.byref(p), ctypes.byref(h)) == 0
+    ldx = 128
+    assert lib.tflbm_state_bytes(h) == per_site * ldx * 30
+    assert lib.tflbm_workspace_bytes(h) >= 2 * per_site * ldx * 30
+    wb = 8 if prec == 0 else 4
+    assert lib.tflbm_capture_bytes(h) == 3 * wb * ldx * 30
+    assert lib.tflbm_adj_bytes(h) >= 2 * 9 * wb * ldx * 30 + 8 * ldx * 30
+    lib.tflbm_destroy(h)
+
+
+def test_call_order_and_null_pointers(lib):
+    h = ctypes.c_void_p()
+    p = params(lib)
+    assert lib.tflbm_create(ctypes.byref(p), ctypes.byref(h)) == 0
+    assert lib.tflbm_create(ctypes.byref(p), None) == _lib.TFLBM_EINVAL
+    # nothing bound / initialised yet: host-side rejections, no GPU touched
+    assert lib.tflbm_bind(h, None, 0) == _lib.TFLBM_EINVAL
+    assert lib.tflbm_bind(h, ctypes.c_void_p(256), 16) == _lib.TFLBM_EINVAL
+    assert lib.tflbm_bind(h, ctypes.c_void_p(257), 1 << 40) == _lib.TFLBM_EINVAL  # misaligned
+    assert lib.tflbm_init(h, ctypes.c_void_p(256), None, None) == _lib.TFLBM_ESTATE
+    assert lib.tflbm_init(h, None, None, None) == _lib.TFLBM_EINVAL
+    assert lib.tflbm_step(h, 1, None) == _lib.TFLBM_ESTATE
+    assert lib.tflbm_step(h, -1, None) == _lib.TFLBM_EINVAL
+    assert lib.tflbm_read(h, None, None, None, None) == _lib.TFLBM_ESTATE
+    m = ctypes.c_double()
+    assert lib.tflbm_mass(h, ctypes.byref(m), None) == _lib.TFLBM_ESTATE
+    assert lib.tflbm_check(h, None) == _lib.TFLBM_ESTATE
+    assert lib.tflbm_adj_step(h, ctypes.c_void_p(256), ctypes.c_void_p(256), None) == _lib.TFLBM_ESTATE
+    assert lib.tflbm_step_count(h) == 0
+    assert lib.tflbm_step_count(None) == -1
+    lib.tflbm_destroy(h)

@@ -1,0 +1,172 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+FP64 storage: max |dh| / max h <= 1e-12 and the same for u after the stated
+number of steps.  FP32 and FP16-shifted storage: error bounds derived in
+tests/gpu_common.py and below.  Grids span several marching strips and row
+chunks with ragged tails, odd widths (the non-vector load path), degenerate
+1 x 1 and 2 x 3 lattices, uniform and per-site theta, gravity and body force.
+"""
+import math
+
+import pytest
+import torch
+
+from gpu_common import banner, fp32_tol, gpu_run, max_rel, oracle_run, random_case
+from oracle import local, lbm
+from paper_1810_07642_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+CASES = [
+    # (ny, nx, steps, params)
+    (70, 150, 200, dict(tau=0.8, gamma=0.01, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5, ay=-2e-5)),
+    (23, 37, 150, dict(tau=1.0, gamma=0.02, g=0.0, hstar=0.2, delta=0.7)),
+    (130, 61, 60, dict(tau=1.3, gamma=0.01, g=-2e-4, hstar=0.15, delta=1.5, ax=-3e-5)),
+    (3, 2, 40, dict(tau=0.9, gamma=0.01, g=1e-3, hstar=0.1, delta=1.0, ay=1e-5)),
+    (1, 1, 30, dict(tau=1.0, gamma=0.01, g=1e-3, hstar=0.1, delta=1.0, ax=1e-4)),
+    (17, 260, 80, dict(tau=1.0, gamma=0.01, g=0.0, hstar=0.1, delta=1.0, n=4, m=3)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_fp64_matches_oracle(case):
+    ny, nx, steps, p = CASES[case]
+    banner(f"fp64 parity case {case}: {ny}x{nx}, {steps} steps")
+    h0, th = random_case(ny, nx, 100 + case)
+    ho, uxo, uyo, mo = oracle_run(p, h0, th, steps)
+    hg, uxg, uyg, mg = gpu_run(p, h0, th, steps, "fp64")
+    assert max_rel(hg, ho) <= TOL64
+    assert max_rel(uxg, uxo) <= TOL64 * 10 or float((uxg - uxo).abs().max()) < 1e-18
+    assert max_rel(uyg, uyo) <= TOL64 * 10 or float((uyg - uyo).abs().max()) < 1e-18
+    assert abs(mg - mo) <= 1e-13 * abs(mo)
+
+
+def test_fp64_uniform_theta_path_matches_oracle():
+    ny, nx, steps = 50, 90, 120
+    p = dict(tau=1.0, gamma=0.01, hstar=0.1, delta=1.0, ax=2e-5)
+    h0, _ = random_case(ny, nx, 7)
+    th = torch.full((ny, nx), 0.45, dtype=torch.float64)
+    ho, uxo, uyo, _ = oracle_run(p, h0, th, steps)
+    hg, uxg, uyg, _ = gpu_run(p, h0, th, steps, "fp64", theta_field=False)
+    assert max_rel(hg, ho) <= TOL64
+    assert max_rel(uxg, uxo) <= 10 * TOL64
+
+
+def test_fp64_sessile_drop_2000_steps():
+    """The relaxing drop (64 x 64, cap r = 20 apex 8 on h_* = 0.05, theta =
+    pi/9), 2000 steps, FP64: h and u against the oracle, mass drift."""
+    banner("fp64 sessile drop 64x64 x 2000")
+    p, h0, th = inputs.sessile_drop()
+    ho, uxo, uyo, mo = oracle_run(p, h0, th, 2000)
+    hg, uxg, uyg, mg = gpu_run(p, h0, th, 2000, "fp64")
+    assert max_rel(hg, ho) <= TOL64
+    assert max_rel(uxg, uxo) <= 100 * TOL64
+    assert max_rel(uyg, uyo) <= 100 * TOL64
+    m0 = float(h0.sum())
+    assert abs(mg - m0) <= 1e-13 * m0
+
+
+@pytest.mark.parametrize("case", [0, 1, 2, 5])
+def test_fp32_matches_oracle(case):
+    ny, nx, steps, p = CASES[case]
+    banner(f"fp32 parity case {case}")
+    h0, th = random_case(ny, nx, 100 + case)
+    ho, uxo, uyo, mo = oracle_run(p, h0, th, steps)
+    hg, uxg, uyg, mg = gpu_run(p, h0, th, steps, "fp32")
+    err = max_rel(hg, ho)
+    print(f"fp32 case {case}: max|dh|/max h = {err:.3e} (bound {fp32_tol(steps):.3e})")
+    assert err <= fp32_tol(steps)
+
+
+@pytest.mark.parametrize("case", [0, 1, 2, 5])
+def test_fp16s_matches_oracle(case):
+    """FP16-shifted storage: the moving populations carry a relative error of
+    2^-12 (round to nearest, 11-bit significand) each time they are stored;
+    8 of them feed each new h, so per step |dh| <= 8 * 2^-12 * max|f_l>0|,
+    accumulated linearly, on top of the FP32 bound."""
+    ny, nx, steps, p = CASES[case]
+    banner(f"fp16s parity case {case}")
+    h0, th = random_case(ny, nx, 100 + case)
+    P = lbm.Params(**p)
+    f = lbm.run(lbm.init(h0, P), lbm.kappa(th, P), P, steps)
+    fmov = float(f[1:].abs().max())
+    ho, uxo, uyo = lbm.readout(f)
+    hg, uxg, uyg, mg = gpu_run(p, h0, th, steps, "fp16s", fp16_scale_log2=14)
+    err = float((hg - ho).abs().max())
+    bound = fp32_tol(steps) * float(ho.abs().max()) + steps * 8 * 2.0 ** -12 * fmov
+    print(f"fp16s case {case}: max|dh| = {err:.3e} (bound {bound:.3e}, max|f_moving| = {fmov:.2e})")
+    assert err <= bound
+
+
+def test_flat_film_stays_flat_all_forms():
+    for prec in ("fp64", "fp32", "fp16s"):
+        p = dict(tau=1.2, gamma=0.01, hstar=0.05, g=1e-4, delta=1.0)
+        h0 = torch.full((40, 130), 0.37, dtype=torch.float64)
+        th = torch.full_like(h0, 0.5)
+        hg, uxg, uyg, _ = gpu_run(p, h0, th, 100, prec)
+        tol = 1e-13 if prec == "fp64" else 1e-5
+        assert float((hg - 0.37).abs().max()) <= tol * 0.37
+        assert float(uxg.abs().max()) <= tol and float(uyg.abs().max()) <= tol
+
+
+def test_full_size_dewetting_sampled_sites():
+    """The 4096 x 4096 patterned-dewetting workload in the launch shape the
+    benchmark times: 5 FP32 steps and 5 FP64 steps, checked against the
+    oracle at 48 seeded sites (periodic windows, oracle/local.py)."""
+    banner("full-size 4096^2 sampled parity")
+    p, h0, th = inputs.patterned_dewetting()
+    steps = 5
+    sites = inputs.random_pixels(4096, 4096, 44, seed=9) + [(0, 0), (4095, 4095), (0, 4095), (2048, 123)]
+    hs, uxs, uys = local.sampled_run(h0, th, lbm.Params(**p), steps, sites)
+    ys = torch.tensor([s[0] for s in sites])
+    xs = torch.tensor([s[1] for s in sites])
+    for prec, tol in (("fp64", TOL64), ("fp32", fp32_tol(steps))):
+        hg, uxg, uyg, _ = gpu_run(p, h0, th, steps, prec)
+        err = max_rel(hg[ys, xs], hs)
+        print(f"4096^2 {prec}: sampled max|dh|/max h = {err:.3e}")
+        assert err <= tol
+        if prec == "fp64":
+            assert max_rel(uxg[ys, xs], uxs) <= 1e-9
+            assert max_rel(uyg[ys, xs], uys) <= 1e-9
+        del hg, uxg, uyg
+        torch.cuda.empty_cache()
+
+
+def test_nonfinite_and_nonpositive_heights_flagged():
+    from paper_1810_07642_amd import Sim, TFLBMError
+    from paper_1810_07642_amd._lib import TFLBM_ENONFINITE
+    for bad in (float("nan"), -0.1, 0.0, float("inf")):
+        h0 = torch.full((16, 70), 0.3, dtype=torch.float64)
+        h0[5, 33] = bad
+        sim = Sim(70, 16, "fp32", hstar=0.1)
+        sim.init(h0, None)
+        assert sim.status() == TFLBM_ENONFINITE
+        with pytest.raises(TFLBMError):
+            sim.check()
+    sim = Sim(70, 16, "fp32", hstar=0.1)
+    sim.init(torch.full((16, 70), 0.3, dtype=torch.float64), None)
+    sim.step(10)
+    sim.check()
+
+
+def test_checkpoint_restore_is_bitwise_and_runs_are_deterministic():
+    from paper_1810_07642_amd import Sim
+    for prec in ("fp64", "fp32", "fp16s"):
+        p = dict(tau=0.9, gamma=0.01, hstar=0.1, delta=1.0, ax=1e-5)
+        h0, th = random_case(90, 140, 3)
+        a = Sim(140, 90, prec, **p).init(h0, th)
+        a.step(30)
+        ck = a.state_save()
+        a.step(40)
+        ha = a.height().cpu()
+        b = Sim(140, 90, prec, **p).init(h0, th)
+        b.step(5)
+        b.state_load(ck, 30)
+        b.step(40)
+        assert b.steps == 70
+        assert torch.equal(b.height().cpu(), ha)
+        c = Sim(140, 90, prec, **p).init(h0, th)
+        c.step(70)
+        assert torch.equal(c.height().cpu(), ha)
