@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Throughput of the thin-film lattice Boltzmann step on one MI355X.
+
+Workload (the headline configuration): patterned-substrate dewetting on a
+4096 x 4096 periodic lattice, FP32 population storage, contact-angle stripes
+of period 256 alternating pi/9 and pi/4 (sine-smoothed edges, width 8), flat
+film h0 = 0.1 + 1e-4 U(-1, 1) (seed 2), h_* = 0.09, gamma = 0.01, tau = 1,
+delta = 1.  A "step" is one lattice time step of the whole grid (one launch
+of the fused step kernel); MLUPS = nx ny steps / (t 1e6) (Sec. IV of the paper).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  Besides the headline FP32 number it reports the FP64
+and FP16-shifted forms, their errors against the FP64 path, the FP32/FP64
+speed-up, the adjoint/forward time ratio of the inverse-design case
+(512 x 512, 4096 steps, checkpoints every 64), the roofline position of the
+step kernel and the FP64 CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
+BYTES_PER_SITE = {"fp64": 152, "fp32": 76, "fp16s": 44}  # read + write 9 populations, + kappa field
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "step_fp32_dewetting4096_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1810_07642_amd", "csrc", f) for f in ("fwd.hip", "device.h")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    if not os.path.exists(PROFILE_SUMMARY):
+        return None
+    text = open(PROFILE_SUMMARY).read()
+    m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_val.group(1))
+
+
+def timed_steps(sim, steps, warmup):
+    import torch
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)  # ms
+
+
+def run_form(prec, p, h0, th, steps, warmup):
+    from paper_1810_07642_amd import Sim
+    import torch
+    n = h0.shape[0]
+    sim = Sim(n, n, prec, **p).init(h0, th)
+    ms = timed_steps(sim, steps, warmup)
+    sim.check()
+    h = sim.height()
+    mass = sim.mass()
+    del sim
+    torch.cuda.empty_cache()
+    return ms, h, mass
+
+
+def adjoint_ratio(prec="fp32", n=512, steps=4096, K=64):
+    """Backward (recompute + adjoint) over forward (with checkpoints) wall time
+    of the inverse-design case."""
+    import torch
+    from paper_1810_07642_amd import TFLBMRun, inputs
+    p, h0, th, target = inputs.inverse_design(n=n)
+    tgt = target.cuda()
+    res = []
+    for _ in range(2):  # first pass warms up
+        h0c = h0.cuda().requires_grad_(True)
+        thc = th.cuda().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = TFLBMRun.apply(h0c, thc, p, steps, K, prec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss = 0.5 * ((h - tgt) ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res.append((t1 - t0, t2 - t1))
+    fwd, bwd = res[-1]
+    return {"forward_s": fwd, "backward_s": bwd, "ratio": bwd / fwd, "grid": n, "steps": steps,
+            "checkpoint_every": K, "storage": prec}
+
+
+def cpu_baseline(p, h0, th, budget_s=12.0):
+    """The FP64 oracle (never tuned) on the host cores: whole steps of the same
+    4096 x 4096 workload until ~budget_s of CPU work, at least two."""
+    import torch
+    from oracle import lbm
+    P = lbm.Params(**p)
+    kap = lbm.kappa(th, P)
+    f = lbm.init(h0, P)
+    t0 = time.perf_counter()
+    done = 0
+    while done < 2 or (time.perf_counter() - t0 < budget_s and done < 6):
+        f = lbm.step(f, kap, P)
+        done += 1
+    dt = time.perf_counter() - t0
+    n = h0.numel()
+    return {"value": n * done / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{done} whole steps of the {h0.shape[1]}x{h0.shape[0]} dewetting workload, FP64, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--n", type=int, default=4096, help="lattice side (default 4096)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="headline FP32 number only")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="run this many FP32 steps and a 1 GiB device copy (for rocprofv3), then exit")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the thin-film step runs on a single MI355X in this build "
+              "(multi-GPU slab decomposition is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1810_07642_amd import Sim, inputs
+
+    n = args.n
+    p, h0, th = inputs.patterned_dewetting(n=n)
+
+    if args.profile_steps:
+        sim = Sim(n, n, "fp32", **p).init(h0, th)
+        sim.step(args.profile_steps)
+        torch.cuda.synchronize()
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"profile run: {args.profile_steps} fp32 steps at {n}^2 and a 1 GiB copy")
+        return
+
+    ms32, h32, m32 = run_form("fp32", p, h0, th, args.steps, args.warmup)
+    ms_step = ms32 / args.steps
+    sites = n * n
+    mlups = sites * args.steps / (ms32 * 1e-3) / 1e6
+    achieved = BYTES_PER_SITE["fp32"] * sites / (ms_step * 1e-3) / 1e9
+    traffic = committed_traffic()
+    line = {
+        "metric": "D2Q9 thin-film MLUPS, % HBM roofline, FP32/FP64 speedup, adjoint/forward time",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"patterned-substrate dewetting {n}x{n}, FP32 storage, stripe theta field",
+                   "nx": n, "ny": n, "storage": "fp32", "theta": "stripes pi/9 | pi/4, period 256",
+                   "hstar": p["hstar"], "tau": p["tau"], "gamma": p["gamma"], "delta": p["delta"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / (ms_step * 1e-3) / 1e9, 1),
+                     "kernel": "step_kernel<fp32, kappa field>", "bytes_per_site": BYTES_PER_SITE["fp32"]},
+    }
+    log(f"fp32: {ms_step * 1e3:.1f} us/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic")
+
+    if not args.no_extras:
+        extras = {}
+        k64 = max(50, args.steps // 4)
+        ms64, h64, m64 = run_form("fp64", p, h0, th, k64, 20)
+        ms16, h16, m16 = run_form("fp16s", p, h0, th, args.steps, args.warmup)
+        mlups64 = sites * k64 / (ms64 * 1e-3) / 1e6
+        mlups16 = sites * args.steps / (ms16 * 1e-3) / 1e6
+        # accuracy against the FP64 path after the same number of steps
+        from paper_1810_07642_amd import Sim as _S
+        total = args.steps + args.warmup
+        s64 = _S(n, n, "fp64", **p).init(h0, th)
+        s64.step(total)
+        href = s64.height()
+        del s64
+        torch.cuda.empty_cache()
+        scale = float(href.abs().max())
+        extras["fp64"] = {"mlups": round(mlups64, 1), "ms_per_step": round(ms64 / k64, 5),
+                          "hbm_frac": round(BYTES_PER_SITE["fp64"] * mlups64 * 1e6 / 1e9 / HBM_PEAK_GBS, 4)}
+        extras["fp16s"] = {"mlups": round(mlups16, 1), "ms_per_step": round(ms16 / args.steps, 5),
+                           "hbm_frac": round(BYTES_PER_SITE["fp16s"] * mlups16 * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
+                           "max_rel_dh_vs_fp64": float((h16 - href).abs().max()) / scale}
+        extras["fp32_max_rel_dh_vs_fp64"] = float((h32 - href).abs().max()) / scale
+        extras["accuracy_after_steps"] = total
+        extras["fp32_over_fp64_speedup"] = round(mlups / mlups64, 3)
+        extras["fp16s_over_fp64_speedup"] = round(mlups16 / mlups64, 3)
+        m0 = float(h0.sum())
+        extras["mass_rel_drift"] = {"fp32": (m32 - m0) / m0, "fp16s": (m16 - m0) / m0}
+        del h16, href
+        torch.cuda.empty_cache()
+        extras["adjoint"] = adjoint_ratio()
+        line["extras"] = extras
+        log(f"fp64 {mlups64:.0f} MLUPS, fp16s {mlups16:.0f} MLUPS, adjoint/forward {extras['adjoint']['ratio']:.2f}")
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p, h0, th)
+        log(f"cpu oracle: {line['cpu_baseline']['value']:.2f} MLUPS on {line['cpu_baseline']['cores']} threads")
+
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

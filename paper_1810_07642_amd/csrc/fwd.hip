@@ -18,16 +18,45 @@
 // from adjacent lanes (cross-lane shuffles); the three-row windows of h and
 // p stay in registers.  No LDS, no barriers.  The only redundant HBM/L2
 // reads are the 4 halo columns per strip and the 4 halo rows per chunk.
+#include <type_traits>
+
 #include "device.h"
 #include "launch.h"
 
 namespace tflbm {
+
+// Aligned store of one population row for the two-column lanes (V = 2).
+// `val` holds the post-collision values of the lane's own columns (a, a+1);
+// the destination of column c is c + cx.  Each lane writes the aligned pair
+// (col0, col0 + 1) of the destination row, taking the value of the column to
+// its left (cx = +1) or right (cx = -1) from the neighbouring lane, and only
+// the elements whose source column belongs to this strip.  `ok0`/`ok1` tell
+// whether the sources of the two destination elements are in the strip.
+template <typename E>
+__device__ __forceinline__ void store_pair(E *row, int col0, E v0, E v1, bool ok0, bool ok1) {
+  if (ok0 && ok1) {
+    if constexpr (sizeof(E) == 4) *(float2 *)(row + col0) = make_float2(v0, v1);
+    else *(__half2 *)(row + col0) = __halves2half2(v0, v1);
+  } else {
+    if (ok0) row[col0] = v0;
+    if (ok1) row[col0 + 1] = v1;
+  }
+}
+
+__device__ __forceinline__ __half half_from_left(__half v) {
+  return __ushort_as_half((unsigned short)__shfl_up((int)__half_as_ushort(v), 1));
+}
+__device__ __forceinline__ __half half_from_right(__half v) {
+  return __ushort_as_half((unsigned short)__shfl_down((int)__half_as_ushort(v), 1));
+}
 
 template <int P, bool KF, bool CAP>
 __global__ __launch_bounds__(64) void step_kernel(StepArgs A) {
   using T = typename Form<P>::T;
   constexpr int V = Form<P>::V;
   constexpr int OUTW = 64 * V - 4;
+  // populations of rows r-1 and r-2, each lane's own columns
+  __shared__ T hist[2][9][64 * V];
 
   // XCD-aware tile order: consecutive workgroups land on different XCDs
   // (round robin), so give each XCD a contiguous block of tiles.
@@ -43,7 +72,7 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs A) {
   const int lane = threadIdx.x;
   const int nx = A.nx, ny = A.ny, ldx = A.ldx;
 
-  const int a = x0 - 2 + V * lane;
+  const int a = x0 - 2 + V * lane;  // first (unwrapped) column of this lane
   int col[V], colE[V], colW[V];
   bool out[V];
 #pragma unroll
@@ -55,58 +84,83 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs A) {
   }
   bool vec = true;
   if constexpr (V == 2) vec = ((col[0] & 1) == 0) && (col[1] == col[0] + 1);
+  // aligned pair stores need every lane of the wave on an aligned pair
+  const bool pairs = (V == 2) && __all(vec);
+  // sources of the aligned destination pair for cx = +1 and cx = -1
+  const bool srcE0 = (a - 1 >= x0) && (a - 1 < xend);  // column a-1 (cx = +1, element 0)
+  const bool srcW1 = (a + 2 >= x0) && (a + 2 < xend);  // column a+2 (cx = -1, element 1)
 
   const T omega = (T)A.omega, gamma = (T)A.gamma, nu = (T)A.nu, hstar = (T)A.hstar;
-  const T delta = (T)A.delta, ax = (T)A.ax, ay = (T)A.ay, g = (T)A.g;
+  const T ax = (T)A.ax, ay = (T)A.ay, g = (T)A.g;
   const T kap0 = (T)A.kappa0;
   const T cA = (T)(3.0 * kW[1]), cD = (T)(3.0 * kW[2]);  // gradient stencil weights
   const T three_delta2 = (T)(3.0 * A.delta * A.delta), six_delta = (T)(6.0 * A.delta);
   const int n_exp = A.n_exp, m_exp = A.m_exp;
 
-  T fn[9][V], f0[9][V], f1[9][V], f2[9][V];
+  T fa[9][V], fb[9][V];  // rows in flight: r (being consumed) and r+1
   T h0[V + 2], h1[V + 2], h2[V + 2];
   T p1[V + 2], p2[V + 2], p3[V + 2];
   T kn[V], kr[V];
   int bad = 0;
 
   const int K = (yend - y0) + 4;
-  int ry = wrap(y0 - 2, ny);
+  int ry = wrap(y0 - 2, ny);          // row r
+  int rpre = ry + 2 >= ny ? (ry + 2) % ny : ry + 2;  // row r + 2
 #pragma unroll
-  for (int l = 0; l < 9; ++l) Pop<P>::load(A.src, l, A, ry, col, vec, fn[l]);
+  for (int l = 0; l < 9; ++l) Pop<P>::load(A.src, l, A, ry, col, vec, fa[l]);
+  if (K > 1) {
+    const int r1 = ry + 1 == ny ? 0 : ry + 1;
+#pragma unroll
+    for (int l = 0; l < 9; ++l) Pop<P>::load(A.src, l, A, r1, col, vec, fb[l]);
+  }
 
-  for (int k = 0; k < K; ++k) {
-#pragma unroll
-    for (int l = 0; l < 9; ++l)
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        f2[l][v] = f1[l][v];
-        f1[l][v] = f0[l][v];
-        f0[l][v] = fn[l][v];
-      }
-#pragma unroll
-    for (int v = 0; v < V; ++v) kr[v] = kn[v];
-    const int rn = (ry + 1 == ny) ? 0 : ry + 1;
-    if (k + 1 < K) {
-#pragma unroll
-      for (int l = 0; l < 9; ++l) Pop<P>::load(A.src, l, A, rn, col, vec, fn[l]);
-    }
-    if constexpr (KF) {
-      // kappa of row r, used by the pressure of row r in the next iteration
-      const T *kp = (const T *)A.kfield + (size_t)ry * ldx;
-#pragma unroll
-      for (int v = 0; v < V; ++v) kn[v] = kp[col[v]];
-    }
-
+  auto iteration = [&](int k, T(&cur)[9][V]) {
+    const int slot = k & 1;  // LDS slot of row r-2, refilled with row r below
     // h of row r (Sec. II: h = sum_l f_l)
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      T hs = f0[0][v];
+      T hs = cur[0][v];
 #pragma unroll
-      for (int l = 1; l < 9; ++l) hs += f0[l][v];
+      for (int l = 1; l < 9; ++l) hs += cur[l][v];
       h0[1 + v] = hs;
     }
     h0[0] = from_left(h0[V]);
     h0[V + 1] = from_right(h0[1]);
+#pragma unroll
+    for (int v = 0; v < V; ++v) kr[v] = kn[v];
+    if constexpr (KF) {
+      // kappa of row r, used by the pressure of row r in the next iteration
+      const T *kp = (const T *)A.kfield + (size_t)ry * ldx;
+      if constexpr (V == 2) {
+        if (vec) {
+          const float2 kv = *(const float2 *)(kp + col[0]);
+          kn[0] = kv.x;
+          kn[1] = kv.y;
+        } else {
+          kn[0] = kp[col[0]];
+          kn[1] = kp[col[1]];
+        }
+      } else {
+        kn[0] = kp[col[0]];
+      }
+    }
+    // row r-2 leaves the LDS slot that row r takes over
+    T f2[9][V];
+    if (k >= 4) {
+#pragma unroll
+      for (int l = 0; l < 9; ++l)
+#pragma unroll
+        for (int v = 0; v < V; ++v) f2[l][v] = hist[slot][l][V * lane + v];
+    }
+#pragma unroll
+    for (int l = 0; l < 9; ++l)
+#pragma unroll
+      for (int v = 0; v < V; ++v) hist[slot][l][V * lane + v] = cur[l][v];
+    // prefetch row r + 2 into the registers just freed
+    if (k + 2 < K) {
+#pragma unroll
+      for (int l = 0; l < 9; ++l) Pop<P>::load(A.src, l, A, rpre, col, vec, cur[l]);
+    }
 
     if (k >= 2) {
       // film pressure of row r-1 (eqs. "pfilm", "disjoiningP", "n_laplace")
@@ -201,66 +255,71 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs A) {
       }
 
       // streaming: post-collision f_l(x) goes to x + c_l
+      if constexpr (P == kF64) {
 #pragma unroll
-      for (int l = 0; l < 9; ++l) {
-        const int cx = kCx[l], cy = kCy[l];
-        const int yd = cy == 0 ? y : (cy > 0 ? yN : yS);
-        if constexpr (P == kF64) {
+        for (int l = 0; l < 9; ++l) {
+          const int cx = kCx[l], cy = kCy[l];
+          const int yd = cy == 0 ? y : (cy > 0 ? yN : yS);
           double *pl = (double *)(A.dst + plane_offset<P>(l, A.plane)) + (size_t)yd * ldx;
           const int xd = cx == 0 ? col[0] : (cx > 0 ? colE[0] : colW[0]);
           if (out[0]) pl[xd] = post[l][0];
-        } else if constexpr (P == kF32) {
-          float *pl = (float *)(A.dst + plane_offset<P>(l, A.plane)) + (size_t)yd * ldx;
-          if (cx == 0 && vec && out[0] && out[1]) {
-            *(float2 *)(pl + col[0]) = make_float2(post[l][0], post[l][1]);
+        }
+      } else {
+        // FP32 values (FP32 form) or FP16 codes (FP16S form) of the moving
+        // populations; the FP16S rest population absorbs their rounding
+        float rest[V];
+        if constexpr (P == kF16S) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) rest[v] = hv[v];
+        }
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+          if (P == kF16S && l == 0) continue;
+          const int cx = kCx[l], cy = kCy[l];
+          const int yd = cy == 0 ? y : (cy > 0 ? yN : yS);
+          using E = typename std::conditional<P == kF32, float, __half>::type;
+          E e[V];
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            if constexpr (P == kF32) {
+              e[v] = post[l][v];
+            } else {
+              const float s = (float)A.shift[l];
+              e[v] = __float2half_rn((post[l][v] - s) * A.qscale);
+              rest[v] -= s + __half2float(e[v]) * A.qinv;
+            }
+          }
+          E *pl = (E *)(A.dst + plane_offset<P>(l, A.plane)) + (size_t)yd * ldx;
+          if (pairs) {
+            if (cx == 0) {
+              store_pair<E>(pl, col[0], e[0], e[1], out[0], out[1]);
+            } else if (cx > 0) {
+              E left;
+              if constexpr (P == kF32) left = from_left(e[1]);
+              else left = half_from_left(e[1]);
+              store_pair<E>(pl, col[0], left, e[0], srcE0, out[0]);
+            } else {
+              E right;
+              if constexpr (P == kF32) right = from_right(e[0]);
+              else right = half_from_right(e[0]);
+              store_pair<E>(pl, col[0], e[1], right, out[1], srcW1);
+            }
           } else {
 #pragma unroll
             for (int v = 0; v < V; ++v) {
               const int xd = cx == 0 ? col[v] : (cx > 0 ? colE[v] : colW[v]);
-              if (out[v]) pl[xd] = post[l][v];
+              if (out[v]) pl[xd] = e[v];
             }
           }
         }
-      }
-      if constexpr (P == kF16S) {
-        // encode the moving populations; the rest population absorbs their
-        // rounding so that the stored record of the site sums to h
-        __half q[9][V];
-        float rest[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          float sumdq = 0.f;
-#pragma unroll
-          for (int l = 1; l < 9; ++l) {
-            const float s = (float)A.shift[l];
-            q[l][v] = __float2half_rn((post[l][v] - s) * A.qscale);
-            sumdq += s + __half2float(q[l][v]) * A.qinv;
-          }
-          rest[v] = hv[v] - sumdq;
-        }
-        {
+        if constexpr (P == kF16S) {
           float *pl = (float *)A.dst + (size_t)y * ldx;
-          if (vec && out[0] && out[1]) {
-            *(float2 *)(pl + col[0]) = make_float2(rest[0], rest[1]);
+          if (pairs) {
+            store_pair<float>(pl, col[0], rest[0], rest[1], out[0], out[1]);
           } else {
 #pragma unroll
             for (int v = 0; v < V; ++v)
               if (out[v]) pl[col[v]] = rest[v];
-          }
-        }
-#pragma unroll
-        for (int l = 1; l < 9; ++l) {
-          const int cx = kCx[l], cy = kCy[l];
-          const int yd = cy == 0 ? y : (cy > 0 ? yN : yS);
-          __half *pl = (__half *)(A.dst + plane_offset<P>(l, A.plane)) + (size_t)yd * ldx;
-          if (cx == 0 && vec && out[0] && out[1]) {
-            *(__half2 *)(pl + col[0]) = __halves2half2(q[l][0], q[l][1]);
-          } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-              const int xd = cx == 0 ? col[v] : (cx > 0 ? colE[v] : colW[v]);
-              if (out[v]) pl[xd] = q[l][v];
-            }
           }
         }
       }
@@ -284,7 +343,13 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs A) {
       p3[v] = p2[v];
       p2[v] = p1[v];
     }
-    ry = rn;
+    ry = ry + 1 == ny ? 0 : ry + 1;
+    rpre = rpre + 1 == ny ? 0 : rpre + 1;
+  };
+
+  for (int k = 0; k < K; k += 2) {
+    iteration(k, fa);
+    if (k + 1 < K) iteration(k + 1, fb);
   }
 
   const unsigned long long m = __ballot(bad);

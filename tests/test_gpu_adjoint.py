@@ -1,0 +1,116 @@
+"""Reverse mode: the hand-written adjoint of the HIP step (through the C ABI,
+wrapped in TFLBMRun) against the oracle's autograd gradient and against
+central finite differences of the HIP forward."""
+import math
+
+import pytest
+import torch
+
+from gpu_common import banner, random_case
+from oracle import grad as ograd
+from oracle import lbm
+from paper_1810_07642_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    return float((a - b).norm() / b.norm())
+
+
+def gpu_grads(p, h0, th, grad_h, steps, K, prec):
+    from paper_1810_07642_amd import TFLBMRun
+    h0c = h0.cuda().requires_grad_(True)
+    thc = th.cuda().requires_grad_(True)
+    h = TFLBMRun.apply(h0c, thc, p, steps, K, prec)
+    h.backward(grad_h.cuda())
+    torch.cuda.synchronize()
+    return h.detach().cpu(), h0c.grad.cpu(), thc.grad.cpu()
+
+
+CASES = [
+    # ny, nx, steps, K, params
+    (20, 30, 1, 1, dict(tau=1.0, gamma=0.01, g=1e-3, hstar=0.1, delta=1.0, ax=1e-4)),
+    (45, 70, 37, 8, dict(tau=0.8, gamma=0.02, g=-1e-3, hstar=0.15, delta=0.8, ax=2e-5, ay=-1e-5)),
+    (64, 131, 25, 25, dict(tau=1.3, gamma=0.01, g=0.0, hstar=0.2, delta=1.5, n=4, m=3)),
+    (3, 2, 9, 4, dict(tau=0.9, gamma=0.01, g=1e-3, hstar=0.1, delta=1.0)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_fp64_adjoint_matches_oracle_gradient(case):
+    ny, nx, steps, K, p = CASES[case]
+    banner(f"fp64 adjoint case {case}: {ny}x{nx}, {steps} steps, K={K}")
+    h0, th = random_case(ny, nx, 200 + case)
+    g = torch.Generator().manual_seed(300 + case)
+    grad_h = torch.randn((ny, nx), generator=g, dtype=torch.float64)
+    gh0_o, gth_o = ograd.vjp(h0, th, grad_h, lbm.Params(**p), steps, K)
+    _, gh0, gth = gpu_grads(p, h0, th, grad_h, steps, K, "fp64")
+    e0, e1 = rel_l2(gh0, gh0_o), rel_l2(gth, gth_o)
+    print(f"case {case}: rel L2 dL/dh0 {e0:.2e}, dL/dtheta {e1:.2e}")
+    assert e0 <= 1e-11 and e1 <= 1e-11
+    assert float((gh0 - gh0_o).abs().max()) <= 1e-10 * float(gh0_o.abs().max())
+
+
+def test_adjoint_inverse_design_64_copy():
+    """The inverse-design case on a 64 x 64 copy: dewetting recipe, theta = pi/6,
+    smooth target, L = 1/2 sum (h_N - target)^2, 256 steps checkpointed every 64;
+    FP64 forward against the oracle gradient, and the FP32 forward (FP64
+    gradient accumulation) with its error stated."""
+    p, h0, th, target = inputs.inverse_design(n=64)
+    steps, K = 256, 64
+    P = lbm.Params(**p)
+    loss_o, gh0_o, gth_o = ograd.misfit_grad(h0, th, target, P, steps, K)
+    from paper_1810_07642_amd import TFLBMRun
+    res = {}
+    for prec in ("fp64", "fp32"):
+        h0c = h0.cuda().requires_grad_(True)
+        thc = th.cuda().requires_grad_(True)
+        h = TFLBMRun.apply(h0c, thc, p, steps, K, prec)
+        loss = 0.5 * ((h - target.cuda()) ** 2).sum()
+        loss.backward()
+        res[prec] = (float(loss), rel_l2(h0c.grad.cpu(), gh0_o), rel_l2(thc.grad.cpu(), gth_o))
+        print(f"{prec}: loss {res[prec][0]:.10e} (oracle {loss_o:.10e}), rel L2 err dh0 {res[prec][1]:.2e} dtheta {res[prec][2]:.2e}")
+    assert abs(res["fp64"][0] - loss_o) <= 1e-12 * loss_o
+    assert res["fp64"][1] <= 1e-10 and res["fp64"][2] <= 1e-10
+    assert res["fp32"][1] <= 1e-3 and res["fp32"][2] <= 1e-3
+
+
+def test_adjoint_against_finite_differences_fp64():
+    """Central differences of the HIP FP64 forward at 16 seeded pixels for theta
+    and h0 (eps = 1e-4 and eps/2 must agree first), 128 x 128 dewetting recipe,
+    512 steps, K = 64."""
+    from paper_1810_07642_amd import Sim, TFLBMRun
+    p, h0, th, target = inputs.inverse_design(n=128)
+    steps, K = 512, 64
+    h0c = h0.cuda().requires_grad_(True)
+    thc = th.cuda().requires_grad_(True)
+    tgt = target.cuda()
+    h = TFLBMRun.apply(h0c, thc, p, steps, K, "fp64")
+    (0.5 * ((h - tgt) ** 2).sum()).backward()
+    gh0, gth = h0c.grad.cpu(), thc.grad.cpu()
+
+    def loss(hh0, tth):
+        sim = Sim(128, 128, "fp64", **p).init(hh0, tth)
+        sim.step(steps)
+        return float(0.5 * ((sim.height() - tgt) ** 2).sum())
+
+    pix = inputs.random_pixels(128, 128, 16, seed=5)
+    checked = 0
+    for (y, x) in pix:
+        for which, g in (("h0", gh0), ("theta", gth)):
+            fds = []
+            for eps in (1e-4, 5e-5):
+                a = h0.clone(); b = th.clone()
+                c = h0.clone(); d = th.clone()
+                if which == "h0":
+                    a[y, x] += eps; c[y, x] -= eps
+                else:
+                    b[y, x] += eps; d[y, x] -= eps
+                fds.append((loss(a, b) - loss(c, d)) / (2 * eps))
+            scale = float(g.abs().max())
+            if abs(fds[0] - fds[1]) > 1e-6 * scale:
+                continue  # FD itself not converged at this pixel
+            checked += 1
+            assert abs(fds[1] - float(g[y, x])) <= 1e-5 * scale, (which, y, x, fds, float(g[y, x]))
+    assert checked >= 24
