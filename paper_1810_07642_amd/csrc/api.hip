@@ -46,6 +46,7 @@ StepArgs make_step_args(const tflbm_sim *s) {
   A.ny = s->p.ny;
   A.ldx = s->ldx;
   A.plane = s->plane;
+  A.nblk = s->nblk;
   A.nstrips = s->nstrips;
   A.H = s->rows;
   A.ntiles = s->ntiles;
@@ -137,7 +138,8 @@ int tflbm_create(const tflbm_params *p, tflbm_sim **out) {
   s->ldx = (p->nx + 63) / 64 * 64;
   s->plane = (int64_t)p->ny * s->ldx;
   const size_t P = (size_t)s->plane;
-  s->pop_bytes = p->prec == TFLBM_FP64 ? 72 * P : (p->prec == TFLBM_FP32 ? 36 * P : 20 * P);
+  s->nblk = (p->nx + record_sites(p->prec) - 1) / record_sites(p->prec);
+  s->pop_bytes = (size_t)p->ny * s->nblk * record_bytes(p->prec);
   s->kf_bytes = (size_t)work_bytes(p->prec) * P;
   s->n_partials = 1024;
   size_t o = 0;
@@ -150,8 +152,7 @@ int tflbm_create(const tflbm_params *p, tflbm_sim **out) {
   s->ws_bytes = o;
   s->kconst = (double)((p->n_exp - 1) * (p->m_exp - 1)) / ((double)(p->n_exp - p->m_exp) * p->hstar);
   s->kappa0 = (1.0 - std::cos(p->theta0)) * s->kconst;
-  const int outw = step_columns_per_strip(p->prec);
-  s->nstrips = (p->nx + outw - 1) / outw;
+  s->nstrips = s->nblk;  // one marching strip per record column
   s->rows = choose_rows(p->ny, s->nstrips, "TFLBM_ROWS");
   s->ntiles = s->nstrips * ((p->ny + s->rows - 1) / s->rows);
   s->per_xcd = (s->ntiles + 7) / 8;

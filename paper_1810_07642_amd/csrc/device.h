@@ -22,26 +22,106 @@ constexpr double kCs2 = 1.0 / 3.0;
 // Storage form of the populations.
 //  V  : consecutive columns owned by one lane of a marching wavefront.
 //  T  : arithmetic type of the step.
+//  B  : sites per record (one marching strip writes exactly one record per
+//       row); a population segment of a record is B elements long and a whole
+//       number of 128-byte lines, so every store covers complete lines.
+//  RB : bytes per record.
 template <int P> struct Form;
-template <> struct Form<kF64> { using T = double; static constexpr int V = 1; };
-template <> struct Form<kF32> { using T = float; static constexpr int V = 2; };
-template <> struct Form<kF16S> { using T = float; static constexpr int V = 2; };
+template <> struct Form<kF64> {
+  using T = double;
+  static constexpr int V = 1, B = 48, RB = 9 * 48 * 8;
+};
+template <> struct Form<kF32> {
+  using T = float;
+  static constexpr int V = 2, B = 96, RB = 9 * 96 * 4;
+};
+template <> struct Form<kF16S> {
+  using T = float;
+  static constexpr int V = 2, B = 96, RB = 2048;
+};
+
+// Population layout ("pull in x, push in y").  Records of B consecutive
+// columns of one row, [ny][ceil(nx/B)][record].  Population l of site (x, y)
+// is stored in row y at column x - c_lx (periodic): the post-collision value
+// of site (x, y) is written at column x of row y + c_ly, so every lane stores
+// its own columns, and the x shift of streaming is taken on the read side.
+// Inside a record the nine segments are ordered by c_ly (0, +1, -1), so the
+// populations a row writes into each of its three destination rows are
+// contiguous.
+constexpr int kSlot[9] = {0, 1, 3, 4, 5, 2, 6, 7, 8};
+
+// Byte offset of the segment of population l inside a record.
+template <int P> __host__ __device__ constexpr int seg_offset(int l) {
+  if constexpr (P == kF64) return kSlot[l] * 48 * 8;
+  else if constexpr (P == kF32) return kSlot[l] * 96 * 4;
+  else {
+    // FP16S: rest population FP32 (384 B), then FP16 segments of 192 B:
+    // slots 1-2 at 384, slots 3-5 at 768, slots 6-8 at 1408 (each c_ly group
+    // starts on a 128-byte line; the 64 B after slots 3-5 and 6-8 are padding)
+    const int s = kSlot[l];
+    return s == 0 ? 0 : (s <= 2 ? 384 + (s - 1) * 192 : (s <= 5 ? 768 + (s - 3) * 192 : 1408 + (s - 6) * 192));
+  }
+}
 
 // Everything a step kernel needs, passed by value.
 struct StepArgs {
-  const char *src;        // populations at time t (push layout: f_l(x) at x)
-  char *dst;              // populations at time t + 1
+  const char *src;        // population records at time t
+  char *dst;              // population records at time t + 1
   const void *kfield;     // kappa field [ny][ldx] in T, or nullptr for kappa0
   char *capture;          // h, jx, jy planes [3][ny][ldx] in T, or nullptr
   int *flag;              // status word: bit 0 set on h <= 0 or non-finite h
-  int nx, ny, ldx;
+  int nx, ny, ldx;        // ldx: pitch of the plane arrays (kappa, capture)
   int64_t plane;          // ny * ldx elements
+  int nblk;               // records per row, ceil(nx / B)
   int nstrips, H, ntiles, per_xcd;
   int n_exp, m_exp;
   double omega, gamma, nu, hstar, delta, ax, ay, g, kappa0;
   double shift[9];        // FP16S: rest-equilibrium shift of each moving population
   float qscale, qinv;     // FP16S: 2^s and 2^-s
 };
+
+// ---- buffer access ----------------------------------------------------------
+// Raw buffer loads/stores: a wave-uniform resource (base address and byte
+// length, held in scalar registers) and a per-lane 32-bit byte offset, so the
+// hot loop spends no vector instructions on 64-bit address arithmetic.
+// Offsets at or beyond the length read 0 and drop stores.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float ld_f32(rsrc_t r, int off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ float2 ld_f32x2(rsrc_t r, int off) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ double ld_f64(rsrc_t r, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ __half ld_f16(rsrc_t r, int off) {
+  return __ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+}
+__device__ __forceinline__ __half2 ld_f16x2(rsrc_t r, int off) {
+  return __builtin_bit_cast(__half2, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void st_f32(rsrc_t r, int off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void st_f32x2(rsrc_t r, int off, float a, float b) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, make_float2(a, b)), r, off, 0, 0);
+}
+__device__ __forceinline__ void st_f64(rsrc_t r, int off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void st_f16(rsrc_t r, int off, __half v) {
+  __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(v), r, off, 0, 0);
+}
+__device__ __forceinline__ void st_f16x2(rsrc_t r, int off, __half a, __half b) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, __halves2half2(a, b)), r, off, 0, 0);
+}
+__device__ __forceinline__ void st_t(rsrc_t r, int off, float v) { st_f32(r, off, v); }
+__device__ __forceinline__ void st_t(rsrc_t r, int off, double v) { st_f64(r, off, v); }
 
 __device__ __forceinline__ int wrap(int i, int n) {
   int r = i % n;
@@ -51,6 +131,26 @@ __device__ __forceinline__ int wrap(int i, int n) {
 // Value of `v` held by lane - 1 (own value on lane 0) / lane + 1 (own value on lane 63).
 template <typename T> __device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1); }
 template <typename T> __device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1); }
+
+// a * b + c: fused for FP32 (one rounding), two roundings for FP64 so that the
+// FP64 step keeps the unfused arithmetic of its reference.
+__device__ __forceinline__ float madd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double madd(double a, double b, double c) { return a * b + c; }
+
+// 1/x: the hardware reciprocal (about 1 ulp) in FP32, correctly rounded in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// (h_*/h)^n - (h_*/h)^m given r = h_*/h; (9, 3) and (3, 9) without loops.
+template <typename T> __device__ __forceinline__ T ipow(T x, int n);
+template <typename T> __device__ __forceinline__ T disjoining(T r, int n, int m) {
+  if ((n == 9 && m == 3) || (n == 3 && m == 9)) {
+    const T r3 = r * r * r;
+    const T r9 = r3 * r3 * r3;
+    return n == 9 ? r9 - r3 : r3 - r9;
+  }
+  return ipow(r, n) - ipow(r, m);
+}
 
 // x^n for a small non-negative integer n by repeated squaring.
 template <typename T> __device__ __forceinline__ T ipow(T x, int n) {
@@ -64,66 +164,19 @@ template <typename T> __device__ __forceinline__ T ipow(T x, int n) {
   return r;
 }
 
-// ---- population storage -------------------------------------------------
-// Plane l of a buffer: FP64/FP32 planes of T; FP16S: plane 0 FP32, planes
-// 1..8 FP16 stored after it.
-template <int P> __device__ __forceinline__ size_t plane_offset(int l, int64_t plane) {
-  if constexpr (P == kF64) return (size_t)l * plane * 8;
-  else if constexpr (P == kF32) return (size_t)l * plane * 4;
-  else return l == 0 ? 0 : (size_t)plane * 4 + (size_t)(l - 1) * plane * 2;
+// ---- population storage ------------------------------------------------
+// Element of population l at (row y, stored column c), widened to T.
+template <int P>
+__device__ __forceinline__ typename Form<P>::T pop_at(const char *buf, int l, int y, int c, const StepArgs &A) {
+  constexpr int B = Form<P>::B;
+  const int blk = c / B, pos = c - blk * B;
+  const char *rec = buf + ((size_t)y * A.nblk + blk) * Form<P>::RB + seg_offset<P>(l);
+  if constexpr (P == kF64) return ((const double *)rec)[pos];
+  else if constexpr (P == kF32) return ((const float *)rec)[pos];
+  else {
+    if (l == 0) return ((const float *)rec)[pos];
+    return (float)A.shift[l] + __half2float(((const __half *)rec)[pos]) * A.qinv;
+  }
 }
-
-template <int P> struct Pop;
-
-template <> struct Pop<kF64> {
-  __device__ static void load(const char *buf, int l, const StepArgs &A, int row, const int *col,
-                              bool /*vec*/, double *out) {
-    const double *p = (const double *)(buf + plane_offset<kF64>(l, A.plane)) + (size_t)row * A.ldx;
-    out[0] = p[col[0]];
-  }
-};
-
-template <> struct Pop<kF32> {
-  __device__ static void load(const char *buf, int l, const StepArgs &A, int row, const int *col,
-                              bool vec, float *out) {
-    const float *p = (const float *)(buf + plane_offset<kF32>(l, A.plane)) + (size_t)row * A.ldx;
-    if (vec) {
-      float2 v = *(const float2 *)(p + col[0]);
-      out[0] = v.x;
-      out[1] = v.y;
-    } else {
-      out[0] = p[col[0]];
-      out[1] = p[col[1]];
-    }
-  }
-};
-
-template <> struct Pop<kF16S> {
-  __device__ static void load(const char *buf, int l, const StepArgs &A, int row, const int *col,
-                              bool vec, float *out) {
-    if (l == 0) {
-      const float *p = (const float *)buf + (size_t)row * A.ldx;
-      if (vec) {
-        float2 v = *(const float2 *)(p + col[0]);
-        out[0] = v.x;
-        out[1] = v.y;
-      } else {
-        out[0] = p[col[0]];
-        out[1] = p[col[1]];
-      }
-    } else {
-      const __half *p = (const __half *)(buf + plane_offset<kF16S>(l, A.plane)) + (size_t)row * A.ldx;
-      float s = (float)A.shift[l];
-      if (vec) {
-        __half2 v = *(const __half2 *)(p + col[0]);
-        out[0] = s + __low2float(v) * A.qinv;
-        out[1] = s + __high2float(v) * A.qinv;
-      } else {
-        out[0] = s + __half2float(p[col[0]]) * A.qinv;
-        out[1] = s + __half2float(p[col[1]]) * A.qinv;
-      }
-    }
-  }
-};
 
 }  // namespace tflbm

@@ -7,8 +7,10 @@
 
 namespace tflbm {
 
-// Output columns of one marching strip for a storage form.
-int step_columns_per_strip(int prec);
+// Sites per population record (= output columns of one marching strip) and
+// bytes per record, for a storage form.
+int record_sites(int prec);
+int record_bytes(int prec);
 
 hipError_t launch_step(int prec, const StepArgs &A, bool kfield, bool capture, hipStream_t s);
 hipError_t launch_init(int prec, const StepArgs &A, const double *h0, const double *theta, double kconst,

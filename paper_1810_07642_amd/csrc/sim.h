@@ -10,6 +10,7 @@ struct tflbm_sim {
   tflbm_params p;
   int ldx = 0;            // row pitch in elements (nx rounded up to 64)
   int64_t plane = 0;      // ny * ldx
+  int nblk = 0;           // population records per row
   size_t pop_bytes = 0;   // one population buffer
   size_t kf_bytes = 0;    // kappa field
   size_t off_a = 0, off_b = 0, off_k = 0, off_flag = 0, off_part = 0, off_out = 0, ws_bytes = 0;

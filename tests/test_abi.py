@@ -74,14 +74,21 @@ def test_friction_stability_warning(lib):
     assert lib.tflbm_check_params(ctypes.byref(params(lib, delta=0.5))) == _lib.TFLBM_OK
 
 
+# population records: (sites per record, bytes per record) of each storage form
+RECORDS = {0: (48, 9 * 48 * 8), 1: (96, 9 * 96 * 4), 2: (96, 2048)}
+
+
 @pytest.mark.parametrize("prec,per_site", [(0, 72), (1, 36), (2, 20)])
 def test_workspace_and_state_sizes(lib, prec, per_site):
     p = params(lib, prec=prec, nx=100, ny=30)
     h = ctypes.c_void_p()
     assert lib.tflbm_create(ctypes.byref(p), ctypes.byref(h)) == 0
     ldx = 128
-    assert lib.tflbm_state_bytes(h) == per_site * ldx * 30
-    assert lib.tflbm_workspace_bytes(h) >= 2 * per_site * ldx * 30
+    B, RB = RECORDS[prec]
+    nblk = -(-100 // B)
+    assert lib.tflbm_state_bytes(h) == 30 * nblk * RB
+    assert RB >= per_site * B
+    assert lib.tflbm_workspace_bytes(h) >= 2 * 30 * nblk * RB
     wb = 8 if prec == 0 else 4
     assert lib.tflbm_capture_bytes(h) == 3 * wb * ldx * 30
     assert lib.tflbm_adj_bytes(h) >= 2 * 9 * wb * ldx * 30 + 8 * ldx * 30
