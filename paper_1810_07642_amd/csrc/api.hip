@@ -20,21 +20,45 @@ int hip_status(const tflbm_sim *s, hipError_t e) {
   return TFLBM_EHIP;
 }
 
-int choose_rows(int ny, int nstrips, const char *env_name) {
+int choose_rows(int ny, int nstrips, int slots, int min_rows, const char *env_name) {
   if (const char *e = std::getenv(env_name)) {
     const int r = std::atoi(e);
     if (r > 0) return r < ny ? r : ny;
   }
-  // aim at ~2048 marching wavefronts (8 per CU) with chunks of 16..128 rows
-  const int want_chunks = (2048 + nstrips - 1) / nstrips;
-  int rows = (ny + want_chunks - 1) / want_chunks;
-  if (rows < 16) rows = 16;
-  if (rows > 128) rows = 128;
+  // As many row chunks as fit in one round of resident wavefronts: a second,
+  // partly filled round would leave most of the GPU idle at the end.
+  int chunks = slots / (nstrips > 0 ? nstrips : 1);
+  if (chunks < 1) chunks = 1;
+  int rows = (ny + chunks - 1) / chunks;
+  if (rows < min_rows) rows = min_rows;
   if (rows > ny) rows = ny;
   return rows;
 }
 
-StepArgs make_step_args(const tflbm_sim *s) {
+// Launch shapes of the step kernels for the device current at the call.
+void plan_launches(tflbm_sim *s) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  const int ny = s->p.ny;
+  int occ1 = step_blocks_per_cu(s->p.prec, s->kfield, 1);
+  int occ2 = step_blocks_per_cu(s->p.prec, s->kfield, 2);
+  if (occ1 <= 0) occ1 = 8;
+  if (occ2 <= 0) occ2 = 8;
+  s->rows = choose_rows(ny, s->nstrips, occ1 * cus, 8, "TFLBM_ROWS");
+  s->ntiles = s->nstrips * ((ny + s->rows - 1) / s->rows);
+  s->per_xcd = (s->ntiles + 7) / 8;
+  s->rows2 = choose_rows(ny, s->nstrips, occ2 * cus, 16, "TFLBM_ROWS2");
+  s->ntiles2 = s->nstrips * ((ny + s->rows2 - 1) / s->rows2);
+  s->per_xcd2 = (s->ntiles2 + 7) / 8;
+  s->adj_rows = choose_rows(ny, s->adj_nstrips, 2 * cus * 4, 8, "TFLBM_ADJ_ROWS");
+  s->adj_ntiles = s->adj_nstrips * ((ny + s->adj_rows - 1) / s->adj_rows);
+  s->adj_per_xcd = (s->adj_ntiles + 7) / 8;
+}
+
+StepArgs make_step_args(const tflbm_sim *s, int ns) {
   StepArgs A;
   std::memset(&A, 0, sizeof(A));
   A.src = s->ws + (s->cur == 0 ? s->off_a : s->off_b);
@@ -48,9 +72,9 @@ StepArgs make_step_args(const tflbm_sim *s) {
   A.plane = s->plane;
   A.nblk = s->nblk;
   A.nstrips = s->nstrips;
-  A.H = s->rows;
-  A.ntiles = s->ntiles;
-  A.per_xcd = s->per_xcd;
+  A.H = ns == 2 ? s->rows2 : s->rows;
+  A.ntiles = ns == 2 ? s->ntiles2 : s->ntiles;
+  A.per_xcd = ns == 2 ? s->per_xcd2 : s->per_xcd;
   A.n_exp = s->p.n_exp;
   A.m_exp = s->p.m_exp;
   A.omega = 1.0 / s->p.tau;
@@ -63,8 +87,8 @@ StepArgs make_step_args(const tflbm_sim *s) {
   A.g = s->p.g;
   A.kappa0 = s->kappa0;
   const double gh2 = s->p.g * s->p.fp16_href * s->p.fp16_href;
-  A.shift[0] = 0.0;
-  for (int l = 1; l < 9; ++l) A.shift[l] = (l & 1) ? gh2 / 6.0 : gh2 / 24.0;
+  A.shift[0] = 0.0f;
+  for (int l = 1; l < 9; ++l) A.shift[l] = (float)((l & 1) ? gh2 / 6.0 : gh2 / 24.0);
   A.qscale = std::ldexp(1.0f, s->p.fp16_scale_log2);
   A.qinv = std::ldexp(1.0f, -s->p.fp16_scale_log2);
   return A;
@@ -153,14 +177,9 @@ int tflbm_create(const tflbm_params *p, tflbm_sim **out) {
   s->kconst = (double)((p->n_exp - 1) * (p->m_exp - 1)) / ((double)(p->n_exp - p->m_exp) * p->hstar);
   s->kappa0 = (1.0 - std::cos(p->theta0)) * s->kconst;
   s->nstrips = s->nblk;  // one marching strip per record column
-  s->rows = choose_rows(p->ny, s->nstrips, "TFLBM_ROWS");
-  s->ntiles = s->nstrips * ((p->ny + s->rows - 1) / s->rows);
-  s->per_xcd = (s->ntiles + 7) / 8;
+  if (const char *e = std::getenv("TFLBM_FUSE")) s->fuse = std::atoi(e) == 1 ? 1 : 2;
   const int aw = adj_columns_per_strip();
   s->adj_nstrips = (p->nx + aw - 1) / aw;
-  s->adj_rows = choose_rows(p->ny, s->adj_nstrips, "TFLBM_ADJ_ROWS");
-  s->adj_ntiles = s->adj_nstrips * ((p->ny + s->adj_rows - 1) / s->adj_rows);
-  s->adj_per_xcd = (s->adj_ntiles + 7) / 8;
   *out = s;
   return TFLBM_OK;
 }
@@ -185,6 +204,7 @@ int tflbm_init(tflbm_sim *sim, const double *d_h0, const double *d_theta, tflbm_
   hipStream_t st = (hipStream_t)stream;
   sim->cur = 1;  // init writes into the "dst" of a cur=1 state, i.e. buffer A
   sim->kfield = d_theta != nullptr;
+  plan_launches(sim);
   StepArgs A = make_step_args(sim);
   int rc = hip_status(sim, hipMemsetAsync(sim->ws + sim->off_flag, 0, 256, st));
   if (rc) return rc;
@@ -202,7 +222,18 @@ static int run_steps(tflbm_sim *sim, int64_t nsteps, void *d_capture, tflbm_stre
   if (!sim->initialised) return TFLBM_ESTATE;
   hipStream_t st = (hipStream_t)stream;
   const size_t cap_bytes = tflbm_capture_bytes(sim);
-  for (int64_t i = 0; i < nsteps; ++i) {
+  int64_t i = 0;
+  if (!d_capture && sim->fuse == 2) {
+    // two fused steps per pass while at least two remain
+    for (; i + 2 <= nsteps; i += 2) {
+      StepArgs A = make_step_args(sim, 2);
+      const int rc = hip_status(sim, launch_step2(sim->p.prec, A, sim->kfield, st));
+      if (rc) return rc;
+      sim->cur ^= 1;
+      sim->steps += 2;
+    }
+  }
+  for (; i < nsteps; ++i) {
     StepArgs A = make_step_args(sim);
     A.capture = d_capture ? (char *)d_capture + (size_t)i * cap_bytes : nullptr;
     const int rc = hip_status(sim, launch_step(sim->p.prec, A, sim->kfield, d_capture != nullptr, st));

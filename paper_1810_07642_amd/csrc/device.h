@@ -36,8 +36,10 @@ template <> struct Form<kF32> {
   static constexpr int V = 2, B = 96, RB = 9 * 96 * 4;
 };
 template <> struct Form<kF16S> {
+  // 2048 bytes of data padded to 17 lines: a power-of-two record stride puts
+  // the same segment of every record on the same few HBM channels
   using T = float;
-  static constexpr int V = 2, B = 96, RB = 2048;
+  static constexpr int V = 2, B = 96, RB = 2176;
 };
 
 // Population layout ("pull in x, push in y").  Records of B consecutive
@@ -76,7 +78,7 @@ struct StepArgs {
   int nstrips, H, ntiles, per_xcd;
   int n_exp, m_exp;
   double omega, gamma, nu, hstar, delta, ax, ay, g, kappa0;
-  double shift[9];        // FP16S: rest-equilibrium shift of each moving population
+  float shift[9];         // FP16S: rest-equilibrium shift of each moving population
   float qscale, qinv;     // FP16S: 2^s and 2^-s
 };
 
@@ -175,7 +177,7 @@ __device__ __forceinline__ typename Form<P>::T pop_at(const char *buf, int l, in
   else if constexpr (P == kF32) return ((const float *)rec)[pos];
   else {
     if (l == 0) return ((const float *)rec)[pos];
-    return (float)A.shift[l] + __half2float(((const __half *)rec)[pos]) * A.qinv;
+    return A.shift[l] + __half2float(((const __half *)rec)[pos]) * A.qinv;
   }
 }
 

@@ -60,7 +60,7 @@ __device__ __forceinline__ void load_raw(rsrc_t row, int l, const int *oe, const
         for (int v = 0; v < V; ++v) out[v] = ld_f32(row, oe[v] + seg);
       }
     } else {
-      const float s = (float)A.shift[l];
+      const float s = A.shift[l];
       if (vec) {
         const __half2 q = ld_f16x2(row, o16[0] + seg);
         out[0] = s + __low2float(q) * A.qinv;
@@ -73,103 +73,77 @@ __device__ __forceinline__ void load_raw(rsrc_t row, int l, const int *oe, const
   }
 }
 
-template <int P, bool KF, bool CAP>
-__global__ __launch_bounds__(64) void step_kernel(StepArgs A) {
+// Per-lane geometry of a marching strip.
+template <int P> struct Lane {
+  static constexpr int V = Form<P>::V;
+  int col[V];         // lattice column of each of the lane's V columns
+  int oe[V], o16[V];  // byte offset in a row of records: working-type and FP16 segments
+  bool out[V];        // the column is an output of this strip
+  bool vec;           // the column pair lies in one record, 8-byte aligned
+  bool vecp;          // the column pair is contiguous and aligned in a plane array
+};
+
+// Step constants in the working type.
+template <typename T> struct Coef {
+  T omega, om1, nu, hstar, ax, ay, kap0, cA, cD, three_delta2, six_delta, mgam, mgam6, g6, g24, g56;
+  int n_exp, m_exp;
+  __device__ explicit Coef(const StepArgs &A) {
+    omega = (T)A.omega;
+    om1 = (T)(1.0 - A.omega);
+    nu = (T)A.nu;
+    hstar = (T)A.hstar;
+    ax = (T)A.ax;
+    ay = (T)A.ay;
+    kap0 = (T)A.kappa0;
+    cA = (T)(3.0 * kW[1]);  // gradient stencil weight on the axes (1/3)
+    cD = (T)(3.0 * kW[2]);  // and on the diagonals (1/12)
+    three_delta2 = (T)(3.0 * A.delta * A.delta);
+    six_delta = (T)(6.0 * A.delta);
+    mgam = (T)(-A.gamma);
+    mgam6 = (T)(-A.gamma / 6.0);
+    g6 = (T)(A.g / 6.0);
+    g24 = (T)(A.g / 24.0);
+    g56 = (T)(5.0 * A.g / 6.0);
+    n_exp = A.n_exp;
+    m_exp = A.m_exp;
+  }
+};
+
+// Values of population l at the lane's own columns, from a row of values held
+// at columns x - c_lx (stored records, or post-collision values before their
+// x streaming): the x shift is a move from the neighbouring lane.
+template <typename T, int V>
+__device__ __forceinline__ void shift_x(int l, const T *in, T *out) {
+  if (kCx[l] == 0) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) out[v] = in[v];
+  } else if (kCx[l] > 0) {
+    out[0] = from_left(in[V - 1]);
+#pragma unroll
+    for (int v = 1; v < V; ++v) out[v] = in[v - 1];
+  } else {
+#pragma unroll
+    for (int v = 0; v < V - 1; ++v) out[v] = in[v + 1];
+    out[V - 1] = from_right(in[0]);
+  }
+}
+
+// One time step applied row by row to a marching strip.  ingest(k, ...)
+// takes the pre-collision populations of the stage's k-th row r and forms
+// h(r); finish(k, ...) forms the film pressure of row r-1 and, for k >= 4,
+// the post-collision populations of row r-2 (eqs. "LBE", "equilibria",
+// "force", "pfilm", "disjoiningP", "forcefric", "alphafric", "derivative",
+// "n_laplace").  The populations of rows r-1 and r-2 wait in two LDS slots.
+template <int P, bool KF> struct Stage {
   using T = typename Form<P>::T;
-  constexpr int V = Form<P>::V;
-  constexpr int B = Form<P>::B;
-  constexpr int RB = Form<P>::RB;
-  constexpr int HX = (64 * V - B) / 2;  // halo columns per side
-  constexpr int ES = sizeof(T);  // bytes per element of the FP32/FP64 segments and plane arrays
-  // assembled populations of rows r-1 and r-2, each lane's own columns
-  __shared__ T hist[2][9][64 * V];
+  static constexpr int V = Form<P>::V;
+  T h0[V + 2], h1[V + 2], h2[V + 2];  // h of rows r, r-1, r-2 with the left/right neighbours
+  T p1[V + 2], p2[V + 2], p3[V + 2];  // p of rows r-1, r-2, r-3
+  T kn[V], kr[V];                     // kappa of rows r and r-1
+  T (*hist)[9][64 * V];
 
-  // XCD-aware tile order: consecutive workgroups land on different XCDs
-  // (round robin), so give each XCD a contiguous block of tiles.
-  const int b = blockIdx.x;
-  const int tile = (b & 7) * A.per_xcd + (b >> 3);
-  if (tile >= A.ntiles) return;
-  const int strip = tile % A.nstrips;
-  const int chunk = tile / A.nstrips;
-  const int x0 = strip * B;
-  const int y0 = chunk * A.H;
-  const int yend = min(y0 + A.H, A.ny);
-  const int xend = min(x0 + B, A.nx);
-  const int lane = threadIdx.x;
-  const int nx = A.nx, ny = A.ny, ldx = A.ldx;
-  const size_t rowB = (size_t)A.nblk * RB;
-  const uint32_t planeRowB = (uint32_t)(ldx * ES);  // one row of a plane array
-
-  const int a = x0 - HX + V * lane;  // first (unwrapped) column of this lane
-  // column, and its byte offset inside a row of records in a segment of the
-  // working type (oe) and in an FP16 segment (o16)
-  int col[V], oe[V], o16[V];
-  bool out[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    col[v] = wrap(a + v, nx);
-    const int blk = col[v] / B;
-    const int pos = col[v] - blk * B;
-    oe[v] = blk * RB + pos * ES;
-    o16[v] = blk * RB + pos * 2;
-    out[v] = (a + v >= x0) && (a + v < xend);
-  }
-  // vector access of the lane's column pair: both in one record, 8-byte aligned
-  bool vec = true;
-  bool vecp = true;  // same for the plane arrays (kappa, capture)
-  if constexpr (V == 2) {
-    vec = (col[1] == col[0] + 1) && (col[0] / B == col[1] / B) && ((col[0] & 1) == 0);
-    vecp = (col[1] == col[0] + 1) && ((col[0] & 1) == 0);
-  }
-
-  const T omega = (T)A.omega, gamma = (T)A.gamma, nu = (T)A.nu, hstar = (T)A.hstar;
-  const T ax = (T)A.ax, ay = (T)A.ay, g = (T)A.g;
-  const T kap0 = (T)A.kappa0;
-  const T cA = (T)(3.0 * kW[1]), cD = (T)(3.0 * kW[2]);  // gradient stencil weights
-  const T three_delta2 = (T)(3.0 * A.delta * A.delta), six_delta = (T)(6.0 * A.delta);
-  const T mgam = -gamma, mgam6 = (T)(-A.gamma / 6.0), om1 = (T)(1.0 - A.omega);
-  const T g6 = (T)(A.g / 6.0), g24 = (T)(A.g / 24.0), g56 = (T)(5.0 * A.g / 6.0);
-  const int n_exp = A.n_exp, m_exp = A.m_exp;
-
-  T fa[9][V], fb[9][V];  // stored values of rows r (being consumed) and r + 1
-  T h0[V + 2], h1[V + 2], h2[V + 2];
-  T p1[V + 2], p2[V + 2], p3[V + 2];
-  T kn[V], kr[V];
-  int bad = 0;
-
-  auto rsrc_src = [&](int row) { return make_rsrc(A.src + row * rowB, (uint32_t)rowB); };
-  auto rsrc_dst = [&](int row) { return make_rsrc(A.dst + row * rowB, (uint32_t)rowB); };
-  const int K = (yend - y0) + 4;
-  int ry = wrap(y0 - 2, ny);                            // row r
-  int rpre = ry + 2 >= ny ? (ry + 2) % ny : ry + 2;     // row r + 2
-#pragma unroll
-  for (int l = 0; l < 9; ++l) load_raw<P>(rsrc_src(ry), l, oe, o16, vec, fa[l], A);
-  if (K > 1) {
-    const int r1 = ry + 1 == ny ? 0 : ry + 1;
-#pragma unroll
-    for (int l = 0; l < 9; ++l) load_raw<P>(rsrc_src(r1), l, oe, o16, vec, fb[l], A);
-  }
-
-  auto iteration = [&](int k, T(&cur)[9][V]) {
-    const int slot = k & 1;  // LDS slot of row r-2, refilled with row r below
-    // populations of the lane's own columns: f_l(x) is stored at x - c_lx
-    T f[9][V];
-#pragma unroll
-    for (int l = 0; l < 9; ++l) {
-      if (kCx[l] == 0) {
-#pragma unroll
-        for (int v = 0; v < V; ++v) f[l][v] = cur[l][v];
-      } else if (kCx[l] > 0) {
-        f[l][0] = from_left(cur[l][V - 1]);
-#pragma unroll
-        for (int v = 1; v < V; ++v) f[l][v] = cur[l][v - 1];
-      } else {
-#pragma unroll
-        for (int v = 0; v < V - 1; ++v) f[l][v] = cur[l][v + 1];
-        f[l][V - 1] = from_right(cur[l][0]);
-      }
-    }
-    // h of row r (Sec. II: h = sum_l f_l)
+  __device__ __forceinline__ void ingest(int k, int ry, const T (&f)[9][V], T (&f2)[9][V], const Lane<P> &L,
+                                         const StepArgs &A, int lane) {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       T hs = f[0][v];
@@ -182,23 +156,24 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs A) {
 #pragma unroll
     for (int v = 0; v < V; ++v) kr[v] = kn[v];
     if constexpr (KF) {
-      // kappa of row r, used by the pressure of row r in the next iteration
-      const rsrc_t kr_row = make_rsrc((const char *)A.kfield + (size_t)ry * planeRowB, planeRowB);
+      // kappa of row r, used by the pressure of row r at the next row
+      const uint32_t prb = (uint32_t)(A.ldx * sizeof(T));
+      const rsrc_t krow = make_rsrc((const char *)A.kfield + (size_t)ry * prb, prb);
       if constexpr (V == 2) {
-        if (vecp) {
-          const float2 kv = ld_f32x2(kr_row, col[0] * 4);
+        if (L.vecp) {
+          const float2 kv = ld_f32x2(krow, L.col[0] * 4);
           kn[0] = kv.x;
           kn[1] = kv.y;
         } else {
-          kn[0] = ld_f32(kr_row, col[0] * 4);
-          kn[1] = ld_f32(kr_row, col[1] * 4);
+          kn[0] = ld_f32(krow, L.col[0] * 4);
+          kn[1] = ld_f32(krow, L.col[1] * 4);
         }
       } else {
-        kn[0] = ld_f64(kr_row, col[0] * 8);
+        kn[0] = ld_f64(krow, L.col[0] * 8);
       }
     }
     // row r-2 leaves the LDS slot that row r takes over
-    T f2[9][V];
+    const int slot = k & 1;
     if (k >= 4) {
 #pragma unroll
       for (int l = 0; l < 9; ++l)
@@ -209,14 +184,12 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs A) {
     for (int l = 0; l < 9; ++l)
 #pragma unroll
       for (int v = 0; v < V; ++v) hist[slot][l][V * lane + v] = f[l][v];
-    // prefetch row r + 2 into the registers just freed
-    if (k + 2 < K) {
-#pragma unroll
-      for (int l = 0; l < 9; ++l) load_raw<P>(rsrc_src(rpre), l, oe, o16, vec, cur[l], A);
-    }
+  }
 
+  __device__ __forceinline__ bool finish(int k, const T (&f2)[9][V], T (&post)[9][V], T (&hv)[V], T (&jxv)[V],
+                                         T (&jyv)[V], const Coef<T> &C, const Lane<P> &L, int &bad) {
     if (k >= 2) {
-      // film pressure of row r-1 (eqs. "pfilm", "disjoiningP", "n_laplace")
+      // film pressure of row r-1: p = -gamma (lap h + kappa phi(h))
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         T odd = h1[v + 2];
@@ -230,26 +203,20 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs A) {
         const T hc = h1[v + 1];
         // 6 lap = 4 sum_axes + sum_diagonals - 20 h
         const T lap6 = madd(T(-20), hc, madd(T(4), odd, even));
-        const T phi = disjoining(hstar * recip(hc), n_exp, m_exp);
-        const T kap = KF ? kr[v] : kap0;
-        p1[v + 1] = madd(mgam6, lap6, mgam * kap * phi);
+        const T phi = disjoining(C.hstar * recip(hc), C.n_exp, C.m_exp);
+        const T kap = KF ? kr[v] : C.kap0;
+        p1[v + 1] = madd(C.mgam6, lap6, C.mgam * kap * phi);
       }
       p1[0] = from_left(p1[V]);
       p1[V + 1] = from_right(p1[1]);
     }
-
-    if (k >= 4) {
-      // collision of row y = r-2, streamed into rows y-1, y, y+1
-      const int y = y0 + (k - 4);
-      const int yN = (y + 1 == ny) ? 0 : y + 1;
-      const int yS = (y == 0) ? ny - 1 : y - 1;
-      T post[9][V];
-      T hv[V], jxv[V], jyv[V];
+    const bool emit = k >= 4;
+    if (emit) {
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        // isotropic gradient of p (eq. "derivative"): axis weight 1/3, diagonal 1/12
-        const T gx = madd(cA, p2[v + 2] - p2[v], cD * ((p1[v + 2] - p1[v]) + (p3[v + 2] - p3[v])));
-        const T gy = madd(cA, p1[v + 1] - p3[v + 1], cD * ((p1[v + 2] - p3[v + 2]) + (p1[v] - p3[v])));
+        // isotropic gradient of p: axis weight 1/3, diagonal 1/12
+        const T gx = madd(C.cA, p2[v + 2] - p2[v], C.cD * ((p1[v + 2] - p1[v]) + (p3[v + 2] - p3[v])));
+        const T gy = madd(C.cA, p1[v + 1] - p3[v + 1], C.cD * ((p1[v + 2] - p3[v + 2]) + (p1[v] - p3[v])));
 
         const T h = h2[1 + v];
         T jx = f2[1][v];
@@ -267,28 +234,27 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs A) {
         const T inv_h = recip(h);
         const T ux = jx * inv_h, uy = jy * inv_h;
 
-        // forces (eqs. "force", "forcefric", "alphafric"):
         // F = h (a - grad p) - nu alpha(h) u, alpha = 6 h / (2 h^2 + 6 delta h + 3 delta^2)
-        const T alpha = T(6) * h * recip(madd(T(2) * h, h, madd(six_delta, h, three_delta2)));
-        const T fric = nu * alpha;
-        const T Fx = madd(h, ax - gx, -fric * ux);
-        const T Fy = madd(h, ay - gy, -fric * uy);
+        const T alpha = T(6) * h * recip(madd(T(2) * h, h, madd(C.six_delta, h, C.three_delta2)));
+        const T fric = C.nu * alpha;
+        const T Fx = madd(h, C.ax - gx, -fric * ux);
+        const T Fy = madd(h, C.ay - gy, -fric * uy);
 
-        // equilibrium (eq. "equilibria", lattice speed 1 in the denominators),
-        // written as h times a polynomial in c.u:
+        // equilibrium (lattice speed 1 in the printed denominators) as h times
+        // a polynomial in c.u:
         //   rest: h (1 - 5 g h/6 - 2 u^2/3)
         //   axes: h ((g h - u^2)/6 + c.u/3 + (c.u)^2/2)
         //   diagonals: h ((g h - u^2)/24 + c.u/12 + (c.u)^2/8)
-        // and BGK with forcing, post = f + omega (feq - f) + 3 w_l c_l.F
+        // BGK with forcing: f + omega (feq - f) + 3 w_l c_l.F
         const T usq = madd(ux, ux, uy * uy);
-        const T a1 = madd(g6, h, usq * T(-1.0 / 6.0));
-        const T a2 = madd(g24, h, usq * T(-1.0 / 24.0));
-        const T hom = h * omega;
+        const T a1 = madd(C.g6, h, usq * T(-1.0 / 6.0));
+        const T a2 = madd(C.g24, h, usq * T(-1.0 / 24.0));
+        const T hom = h * C.omega;
 #pragma unroll
         for (int l = 0; l < 9; ++l) {
           T poly, src;
           if (l == 0) {
-            poly = madd(-g56, h, madd(usq, T(-2.0 / 3.0), T(1)));
+            poly = madd(-C.g56, h, madd(usq, T(-2.0 / 3.0), T(1)));
             src = T(0);
           } else {
             const int cx = kCx[l], cy = kCy[l];
@@ -307,98 +273,262 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs A) {
             }
           }
           // f + omega (h poly - f) + src = (1 - omega) f + (h omega) poly + src
-          post[l][v] = madd(om1, f2[l][v], madd(hom, poly, src));
+          post[l][v] = madd(C.om1, f2[l][v], madd(hom, poly, src));
         }
         hv[v] = h;
         jxv[v] = jx;
         jyv[v] = jy;
-        if (out[v] && !(h > T(0) && h < T(INFINITY))) bad = 1;
-      }
-
-      // streaming: the post-collision f_l of site (x, y) goes to stored
-      // column x of row y + c_ly
-      const bool pair = out[0] && out[V - 1] && vec;
-      const rsrc_t rowD[3] = {rsrc_dst(yS), rsrc_dst(y), rsrc_dst(yN)};  // indexed by c_ly + 1
-      if constexpr (P == kF16S) {
-        float rest[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) rest[v] = hv[v];
-#pragma unroll
-        for (int l = 1; l < 9; ++l) {
-          const rsrc_t rd = rowD[kCy[l] + 1];
-          const int seg = seg_offset<P>(l);
-          const float s = (float)A.shift[l];
-          __half q[V];
-#pragma unroll
-          for (int v = 0; v < V; ++v) {
-            q[v] = __float2half_rn((post[l][v] - s) * A.qscale);
-            rest[v] -= s + __half2float(q[v]) * A.qinv;  // rest population absorbs the rounding
-          }
-          if (pair) {
-            st_f16x2(rd, o16[0] + seg, q[0], q[1]);
-          } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v)
-              if (out[v]) st_f16(rd, o16[v] + seg, q[v]);
-          }
-        }
-        if (pair) {
-          st_f32x2(rowD[1], oe[0], rest[0], rest[1]);
-        } else {
-#pragma unroll
-          for (int v = 0; v < V; ++v)
-            if (out[v]) st_f32(rowD[1], oe[v], rest[v]);
-        }
-        // fill the 64-byte pads after the c_ly = +1 and -1 groups of a full
-        // record so that its lines are written whole
-        if (xend - x0 == B) {
-          const int q16 = lane - HX / V;
-          if (q16 >= 0 && q16 < 16) {
-            const int rec = (x0 / B) * RB;
-            st_f32(rowD[2], rec + 1344 + 4 * q16, 0.f);
-            st_f32(rowD[0], rec + 1984 + 4 * q16, 0.f);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int l = 0; l < 9; ++l) {
-          const rsrc_t rd = rowD[kCy[l] + 1];
-          const int seg = seg_offset<P>(l);
-          if constexpr (P == kF64) {
-            if (out[0]) st_f64(rd, oe[0] + seg, post[l][0]);
-          } else {
-            if (pair) {
-              st_f32x2(rd, oe[0] + seg, post[l][0], post[l][1]);
-            } else {
-#pragma unroll
-              for (int v = 0; v < V; ++v)
-                if (out[v]) st_f32(rd, oe[v] + seg, post[l][v]);
-            }
-          }
-        }
-      }
-      if constexpr (CAP) {
-        const size_t ro = (size_t)y * planeRowB;
-        const rsrc_t c0 = make_rsrc(A.capture + ro, planeRowB);
-        const rsrc_t c1 = make_rsrc(A.capture + (size_t)A.plane * ES + ro, planeRowB);
-        const rsrc_t c2 = make_rsrc(A.capture + 2 * (size_t)A.plane * ES + ro, planeRowB);
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          if (out[v]) {
-            st_t(c0, col[v] * ES, hv[v]);
-            st_t(c1, col[v] * ES, jxv[v]);
-            st_t(c2, col[v] * ES, jyv[v]);
-          }
-        }
+        if (L.out[v] && !(h > T(0) && h < T(INFINITY))) bad = 1;
       }
     }
-
 #pragma unroll
     for (int v = 0; v < V + 2; ++v) {
       h2[v] = h1[v];
       h1[v] = h0[v];
       p3[v] = p2[v];
       p2[v] = p1[v];
+    }
+    return emit;
+  }
+};
+
+// Stores the post-collision populations of row y (values at the lane's own
+// columns) into stored column x of rows y + c_ly.
+template <int P>
+__device__ __forceinline__ void store_row(const StepArgs &A, int y, const typename Form<P>::T (&post)[9][Form<P>::V],
+                                          const typename Form<P>::T (&hv)[Form<P>::V], const Lane<P> &L, int x0,
+                                          int xend, int lane) {
+  constexpr int V = Form<P>::V;
+  constexpr int B = Form<P>::B;
+  constexpr int RB = Form<P>::RB;
+  constexpr int HX = (64 * V - B) / 2;
+  const int ny = A.ny;
+  const size_t rowB = (size_t)A.nblk * RB;
+  const int yN = (y + 1 == ny) ? 0 : y + 1;
+  const int yS = (y == 0) ? ny - 1 : y - 1;
+  const rsrc_t rowD[3] = {make_rsrc(A.dst + yS * rowB, (uint32_t)rowB), make_rsrc(A.dst + y * rowB, (uint32_t)rowB),
+                          make_rsrc(A.dst + yN * rowB, (uint32_t)rowB)};  // indexed by c_ly + 1
+  const bool pair = L.out[0] && L.out[V - 1] && L.vec;
+  if constexpr (P == kF16S) {
+    float rest[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) rest[v] = hv[v];
+#pragma unroll
+    for (int l = 1; l < 9; ++l) {
+      const rsrc_t rd = rowD[kCy[l] + 1];
+      const int seg = seg_offset<P>(l);
+      const float s = A.shift[l];
+      __half q[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        q[v] = __float2half_rn((post[l][v] - s) * A.qscale);
+        rest[v] -= s + __half2float(q[v]) * A.qinv;  // rest population absorbs the rounding
+      }
+      if (pair) {
+        st_f16x2(rd, L.o16[0] + seg, q[0], q[1]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          if (L.out[v]) st_f16(rd, L.o16[v] + seg, q[v]);
+      }
+    }
+    if (pair) {
+      st_f32x2(rowD[1], L.oe[0], rest[0], rest[1]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        if (L.out[v]) st_f32(rowD[1], L.oe[v], rest[v]);
+    }
+    // fill the 64-byte pads after the c_ly = +1 and -1 groups of a full
+    // record so that its lines are written whole
+    if (xend - x0 == B) {
+      const int q16 = lane - HX / V;
+      if (q16 >= 0 && q16 < 16) {
+        const int rec = (x0 / B) * RB;
+        st_f32(rowD[2], rec + 1344 + 4 * q16, 0.f);
+        st_f32(rowD[0], rec + 1984 + 4 * q16, 0.f);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      const rsrc_t rd = rowD[kCy[l] + 1];
+      const int seg = seg_offset<P>(l);
+      if constexpr (P == kF64) {
+        if (L.out[0]) st_f64(rd, L.oe[0] + seg, post[l][0]);
+      } else {
+        if (pair) {
+          st_f32x2(rd, L.oe[0] + seg, post[l][0], post[l][1]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            if (L.out[v]) st_f32(rd, L.oe[v] + seg, post[l][v]);
+        }
+      }
+    }
+  }
+}
+
+// FP16S storage round trip of one row of post-collision values (what a store
+// followed by a load would give): moving populations rounded to FP16 in the
+// shifted, scaled form, rest population h - sum of the decoded moving ones.
+template <int V>
+__device__ __forceinline__ void fp16s_roundtrip(float (&post)[9][V], const float (&hv)[V], const StepArgs &A) {
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    float rest = hv[v];
+#pragma unroll
+    for (int l = 1; l < 9; ++l) {
+      const float s = A.shift[l];
+      const __half q = __float2half_rn((post[l][v] - s) * A.qscale);
+      const float d = s + __half2float(q) * A.qinv;
+      rest -= d;
+      post[l][v] = d;
+    }
+    post[0][v] = rest;
+  }
+}
+
+// NS fused time steps per pass (1 or 2).  Stage 0 consumes the stored rows;
+// with NS = 2 its post-collision rows are streamed in registers into stage 1
+// (rows arrive one row late: row q of the next step needs the post-collision
+// values of rows q-1, q, q+1), whose output is stored.  The strip's chunk
+// reads 2 + 3 (NS - 1) halo rows above and below.
+template <int P, bool KF, bool CAP, int NS>
+__global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
+  using T = typename Form<P>::T;
+  constexpr int V = Form<P>::V;
+  constexpr int B = Form<P>::B;
+  constexpr int RB = Form<P>::RB;
+  constexpr int HX = (64 * V - B) / 2;  // halo columns per side (>= 3 NS)
+  constexpr int ES = sizeof(T);
+  static_assert(HX >= 3 * NS, "halo columns too narrow for the fused steps");
+  __shared__ T hist[NS][2][9][64 * V];
+
+  // XCD-aware tile order: consecutive workgroups land on different XCDs
+  // (round robin), so give each XCD a contiguous block of tiles.
+  const int b = blockIdx.x;
+  const int tile = (b & 7) * A.per_xcd + (b >> 3);
+  if (tile >= A.ntiles) return;
+  const int strip = tile % A.nstrips;
+  const int chunk = tile / A.nstrips;
+  const int x0 = strip * B;
+  const int y0 = chunk * A.H;
+  const int yend = min(y0 + A.H, A.ny);
+  const int xend = min(x0 + B, A.nx);
+  const int lane = threadIdx.x;
+  const int nx = A.nx, ny = A.ny;
+  const size_t rowB = (size_t)A.nblk * RB;
+
+  Lane<P> L;
+  const int a = x0 - HX + V * lane;  // first (unwrapped) column of this lane
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    L.col[v] = wrap(a + v, nx);
+    const int blk = L.col[v] / B;
+    const int pos = L.col[v] - blk * B;
+    L.oe[v] = blk * RB + pos * ES;
+    L.o16[v] = blk * RB + pos * 2;
+    L.out[v] = (a + v >= x0) && (a + v < xend);
+  }
+  L.vec = true;
+  L.vecp = true;
+  if constexpr (V == 2) {
+    L.vec = (L.col[1] == L.col[0] + 1) && (L.col[0] / B == L.col[1] / B) && ((L.col[0] & 1) == 0);
+    L.vecp = (L.col[1] == L.col[0] + 1) && ((L.col[0] & 1) == 0);
+  }
+  const Coef<T> C(A);
+
+  Stage<P, KF> S0;
+  S0.hist = hist[0];
+  Stage<P, KF> S1;
+  if constexpr (NS == 2) S1.hist = hist[1];
+  // post-collision values waiting for the second step, already moved to their
+  // destination columns: c_ly = +1 populations of the last two emitted rows,
+  // c_ly = 0 populations of the last one
+  T pendP1[3][V], pendP2[3][V], pendZ[3][V];
+  int bad = 0;
+
+  constexpr int HALO = 2 + 3 * (NS - 1);
+  const int K = (yend - y0) + 2 * HALO;
+  auto rsrc_src = [&](int row) { return make_rsrc(A.src + row * rowB, (uint32_t)rowB); };
+  T fa[9][V], fb[9][V];  // stored values of rows r (being consumed) and r + 1
+  int ry = wrap(y0 - HALO, ny);                          // row r of stage 0
+  int rpre = ry + 2 >= ny ? (ry + 2) % ny : ry + 2;      // row r + 2
+#pragma unroll
+  for (int l = 0; l < 9; ++l) load_raw<P>(rsrc_src(ry), l, L.oe, L.o16, L.vec, fa[l], A);
+  if (K > 1) {
+    const int r1 = ry + 1 == ny ? 0 : ry + 1;
+#pragma unroll
+    for (int l = 0; l < 9; ++l) load_raw<P>(rsrc_src(r1), l, L.oe, L.o16, L.vec, fb[l], A);
+  }
+
+  auto iteration = [&](int k, T(&cur)[9][V]) {
+    T f[9][V], f2[9][V];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) shift_x<T, V>(l, cur[l], f[l]);
+    S0.ingest(k, ry, f, f2, L, A, lane);
+    // prefetch row r + 2 into the registers just freed
+    if (k + 2 < K) {
+#pragma unroll
+      for (int l = 0; l < 9; ++l) load_raw<P>(rsrc_src(rpre), l, L.oe, L.o16, L.vec, cur[l], A);
+    }
+    T post[9][V], hv[V], jxv[V], jyv[V];
+    if (S0.finish(k, f2, post, hv, jxv, jyv, C, L, bad)) {
+      const int q = y0 - HALO + k - 2;  // row of the post-collision values (unwrapped)
+      if constexpr (NS == 1) {
+        store_row<P>(A, q, post, hv, L, x0, xend, lane);
+        if constexpr (CAP) {
+          const uint32_t prb = (uint32_t)(A.ldx * ES);
+          const size_t ro = (size_t)q * prb;
+          const rsrc_t c0 = make_rsrc(A.capture + ro, prb);
+          const rsrc_t c1 = make_rsrc(A.capture + (size_t)A.plane * ES + ro, prb);
+          const rsrc_t c2 = make_rsrc(A.capture + 2 * (size_t)A.plane * ES + ro, prb);
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            if (L.out[v]) {
+              st_t(c0, L.col[v] * ES, hv[v]);
+              st_t(c1, L.col[v] * ES, jxv[v]);
+              st_t(c2, L.col[v] * ES, jyv[v]);
+            }
+          }
+        }
+      } else {
+        // row q - 1 of the next step is complete: c_ly = +1 populations from
+        // row q - 2, c_ly = 0 from row q - 1, c_ly = -1 from row q
+        const int e = k - 4;  // emission index; q = y0 - 3 + e
+        if constexpr (P == kF16S) fp16s_roundtrip<V>(post, hv, A);  // as if stored and reloaded
+        T g[9][V];
+        shift_x<T, V>(6, post[6], g[6]);
+        shift_x<T, V>(7, post[7], g[7]);
+        shift_x<T, V>(8, post[8], g[8]);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          g[2][v] = pendP2[0][v];
+          g[3][v] = pendP2[1][v];
+          g[4][v] = pendP2[2][v];
+          g[0][v] = pendZ[0][v];
+          g[1][v] = pendZ[1][v];
+          g[5][v] = pendZ[2][v];
+          pendP2[0][v] = pendP1[0][v];
+          pendP2[1][v] = pendP1[1][v];
+          pendP2[2][v] = pendP1[2][v];
+        }
+        shift_x<T, V>(2, post[2], pendP1[0]);
+        shift_x<T, V>(3, post[3], pendP1[1]);
+        shift_x<T, V>(4, post[4], pendP1[2]);
+        shift_x<T, V>(0, post[0], pendZ[0]);
+        shift_x<T, V>(1, post[1], pendZ[1]);
+        shift_x<T, V>(5, post[5], pendZ[2]);
+        if (e >= 2) {
+          const int j = e - 2;  // stage 1 row index; its row is q - 1 = y0 - 2 + j
+          const int rowB1 = wrap(y0 - 2 + j, ny);
+          T g2[9][V];
+          S1.ingest(j, rowB1, g, g2, L, A, lane);
+          T post2[9][V], hv2[V], jx2[V], jy2[V];
+          if (S1.finish(j, g2, post2, hv2, jx2, jy2, C, L, bad)) store_row<P>(A, y0 - 4 + j, post2, hv2, L, x0, xend, lane);
+        }
+      }
     }
     ry = ry + 1 == ny ? 0 : ry + 1;
     rpre = rpre + 1 == ny ? 0 : rpre + 1;
@@ -441,7 +571,7 @@ __global__ void init_kernel(StepArgs A, const double *h0, const double *theta, d
   } else {
     float sumdq = 0.f;
     for (int l = 1; l < 9; ++l) {
-      const float s = (float)A.shift[l];
+      const float s = A.shift[l];
       const __half q = __float2half_rn(((float)e[l] - s) * A.qscale);
       *(__half *)pop_ptr<P>(A.dst, l, y, wrap(x - kCx[l], A.nx), A) = q;
       sumdq += s + __half2float(q) * A.qinv;
@@ -507,24 +637,59 @@ __global__ __launch_bounds__(256) void mass_final_kernel(const double *partial, 
 }
 
 // ---- launchers -----------------------------------------------------------------
-template <int P>
+template <int P, int NS>
 static hipError_t launch_step_p(const StepArgs &A, bool kf, bool cap, hipStream_t s) {
   const dim3 grid(8 * A.per_xcd), block(64);
-  if (kf) {
-    if (cap) step_kernel<P, true, true><<<grid, block, 0, s>>>(A);
-    else step_kernel<P, true, false><<<grid, block, 0, s>>>(A);
+  if constexpr (NS == 1) {
+    if (kf) {
+      if (cap) step_kernel<P, true, true, 1><<<grid, block, 0, s>>>(A);
+      else step_kernel<P, true, false, 1><<<grid, block, 0, s>>>(A);
+    } else {
+      if (cap) step_kernel<P, false, true, 1><<<grid, block, 0, s>>>(A);
+      else step_kernel<P, false, false, 1><<<grid, block, 0, s>>>(A);
+    }
   } else {
-    if (cap) step_kernel<P, false, true><<<grid, block, 0, s>>>(A);
-    else step_kernel<P, false, false><<<grid, block, 0, s>>>(A);
+    if (kf) step_kernel<P, true, false, 2><<<grid, block, 0, s>>>(A);
+    else step_kernel<P, false, false, 2><<<grid, block, 0, s>>>(A);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_step(int prec, const StepArgs &A, bool kf, bool cap, hipStream_t s) {
   switch (prec) {
-    case kF64: return launch_step_p<kF64>(A, kf, cap, s);
-    case kF32: return launch_step_p<kF32>(A, kf, cap, s);
-    default: return launch_step_p<kF16S>(A, kf, cap, s);
+    case kF64: return launch_step_p<kF64, 1>(A, kf, cap, s);
+    case kF32: return launch_step_p<kF32, 1>(A, kf, cap, s);
+    default: return launch_step_p<kF16S, 1>(A, kf, cap, s);
+  }
+}
+
+hipError_t launch_step2(int prec, const StepArgs &A, bool kf, hipStream_t s) {
+  switch (prec) {
+    case kF64: return launch_step_p<kF64, 2>(A, kf, false, s);
+    case kF32: return launch_step_p<kF32, 2>(A, kf, false, s);
+    default: return launch_step_p<kF16S, 2>(A, kf, false, s);
+  }
+}
+
+template <int P>
+static int occupancy_p(bool kf, int ns) {
+  int n = 0;
+  hipError_t e;
+  if (ns == 2) {
+    e = kf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, true, false, 2>, 64, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, false, false, 2>, 64, 0);
+  } else {
+    e = kf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, true, false, 1>, 64, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, false, false, 1>, 64, 0);
+  }
+  return e == hipSuccess ? n : 0;
+}
+
+int step_blocks_per_cu(int prec, bool kf, int ns) {
+  switch (prec) {
+    case kF64: return occupancy_p<kF64>(kf, ns);
+    case kF32: return occupancy_p<kF32>(kf, ns);
+    default: return occupancy_p<kF16S>(kf, ns);
   }
 }
 

@@ -22,8 +22,10 @@ struct tflbm_sim {
   int64_t steps = 0;
   double kconst = 0.0;    // (n - 1)(m - 1)/((n - m) h_*)
   double kappa0 = 0.0;    // kappa of the uniform theta0
-  // launch shape of the forward step
+  // launch shape of the forward step: one step per pass, and two fused steps
   int nstrips = 0, rows = 0, ntiles = 0, per_xcd = 0;
+  int rows2 = 0, ntiles2 = 0, per_xcd2 = 0;
+  int fuse = 2;           // steps fused per pass when possible (1 or 2)
   // reverse pass
   int adj_cur = 0;        // 0: first adjoint buffer holds the current adjoint
   bool adj_seeded = false;
@@ -36,13 +38,18 @@ namespace tflbm {
 // Bytes per element of the working type.
 inline int work_bytes(int prec) { return prec == kF64 ? 8 : 4; }
 
-// StepArgs for the current state of `s` (src = current, dst = other buffer).
-StepArgs make_step_args(const tflbm_sim *s);
+// StepArgs for the current state of `s` (src = current, dst = other buffer),
+// shaped for `ns` fused steps per pass.
+StepArgs make_step_args(const tflbm_sim *s, int ns = 1);
 
 // Records a HIP error on the handle and returns TFLBM_EHIP (or TFLBM_OK).
 int hip_status(const tflbm_sim *s, hipError_t e);
 
-// Rows per chunk of a marching launch with `nstrips` strips over ny rows.
-int choose_rows(int ny, int nstrips, const char *env_name);
+// Rows per chunk of a marching launch with `nstrips` strips over ny rows, given
+// `slots` resident wavefronts; an environment variable may override it.
+int choose_rows(int ny, int nstrips, int slots, int min_rows, const char *env_name);
+
+// Chooses the launch shapes of the step kernels (needs the device).
+void plan_launches(tflbm_sim *s);
 
 }  // namespace tflbm

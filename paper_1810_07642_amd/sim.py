@@ -74,7 +74,8 @@ class Sim:
         _lib.check(self.lib.tflbm_create(ctypes.byref(self.params), ctypes.byref(h)), "tflbm_create")
         self.h = h
         nbytes = self.lib.tflbm_workspace_bytes(h)
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        # zeroed so that record padding (columns past nx) has defined bytes
+        self.ws = torch.zeros(nbytes, dtype=torch.uint8, device=self.device)
         _lib.check(self.lib.tflbm_bind(h, _addr(self.ws), nbytes), "tflbm_bind", h)
         self.h0 = None
         self.theta = None
