@@ -107,11 +107,27 @@ def sessile_drop(n=64, base_radius=20.0, apex=8.0, hstar=0.05, theta=math.pi / 9
     return p, h0, th
 
 
-def rayleigh_taylor(n=512, seed=1, g=-1.0e-4, delta=0.5):
+def lowpass(z, max_mode):
+    """Keeps the Fourier modes of z with |mode number| <= max_mode in each
+    direction (periodic), removes the rest."""
+    ny, nx = z.shape
+    my = torch.fft.fftfreq(ny, dtype=F64).view(-1, 1) * ny
+    mx = torch.fft.fftfreq(nx, dtype=F64).view(1, -1) * nx
+    keep = (my.abs() <= max_mode) & (mx.abs() <= max_mode)
+    return torch.fft.ifft2(torch.fft.fft2(z) * keep).real
+
+
+def rayleigh_taylor(n=512, seed=1, g=-1.0e-4, delta=0.5, max_mode=None):
     """Hanging film: h0 = 1 + 1e-3 U(-1, 1), g = -1e-4 (destabilising),
-    gamma = 0.01, tau = 1, delta = 0.5, no wetting term (theta = 0)."""
+    gamma = 0.01, tau = 1, delta = 0.5, no wetting term (theta = 0).
+    With max_mode set, the noise keeps only Fourier modes up to that mode
+    number (the checkerboard mode of the scheme is unstable for g < 0 and
+    would otherwise grow from the initial noise)."""
     p = params(g=g, delta=delta)
-    h0 = noisy_film(n, n, 1.0, 1.0e-3, seed)
+    z = uniform_noise(n, n, seed)
+    if max_mode is not None:
+        z = lowpass(z, max_mode)
+    h0 = 1.0 + 1.0e-3 * z
     th = torch.zeros((n, n), dtype=F64)
     return p, h0, th
 

@@ -279,3 +279,38 @@ def test_fourier_propagator_tends_to_lubrication_law():
         else:
             hi = mid
     assert abs(lo / math.sqrt(abs(g) / gamma) - 1.0) < 0.01
+
+
+def test_checkerboard_mode_unstable_for_negative_gravity():
+    """The checkerboard mode k = (pi, pi) is invisible to the isotropic
+    gradient stencil (its symbol vanishes there), so the capillary pressure
+    cannot restore it, while a negative g in the equilibrium drives it through
+    streaming: the linearised scheme grows it by about 1 + 2.7|g| per step
+    (1.000267 at g = -1e-4), far faster than the thin-film instability
+    (1.4e-6 per step at the fastest mode).  For g >= 0 it is neutral or damped.
+    The oracle follows the propagator on this mode."""
+    from physics import gradient_symbol
+    sx, sy = gradient_symbol(math.pi, math.pi)
+    assert abs(sx) < 1e-15 and abs(sy) < 1e-15
+    for g, unstable in ((-1e-4, True), (-1e-3, True), (0.0, False), (1e-3, False)):
+        A = fourier_step(math.pi, math.pi, 1.0, 1.0, 0.01, g, 0.0, 0.05, 9, 3, 0.5)
+        lam = np.abs(np.linalg.eigvals(A)).max()
+        assert (lam > 1.0 + 1e-9) == unstable, (g, lam)
+        if unstable:
+            assert abs((lam - 1.0) / abs(g) - 2.667) < 0.05
+    # oracle on an 8 x 8 lattice: the checkerboard amplitude of h after 300 steps
+    n, g, steps, eps = 8, -1e-3, 300, 1e-7
+    p = lbm.Params(tau=1.0, gamma=0.01, g=g, hstar=0.05, delta=0.5)
+    y = torch.arange(n, dtype=F64).view(-1, 1)
+    x = torch.arange(n, dtype=F64).view(1, -1)
+    cb = torch.cos(math.pi * (x + y))
+    h0 = 1.0 + eps * cb
+    f = lbm.init(h0, p)
+    base = lbm.init(torch.ones((n, n), dtype=F64), p)
+    amp0 = np.array([float(((f[l] - base[l]) * cb).mean()) for l in range(9)])
+    A = fourier_step(math.pi, math.pi, 1.0, 1.0, 0.01, g, 0.0, 0.05, 9, 3, 0.5)
+    pred = (np.linalg.matrix_power(A, steps) @ amp0).real
+    f = lbm.run(f, lbm.kappa(torch.zeros((n, n), dtype=F64), p), p, steps)
+    got = np.array([float(((f[l] - base[l]) * cb).mean()) for l in range(9)])
+    assert np.abs(got - pred).max() <= 1e-5 * np.abs(pred).max()
+    assert abs(got.sum()) > 1.5 * abs(amp0.sum())  # the h mode has grown
