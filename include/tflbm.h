@@ -57,11 +57,22 @@ enum {
 };
 
 /* Population storage forms.  Arithmetic is FP64 for TFLBM_FP64 and FP32 otherwise.
- * TFLBM_FP16S stores the rest population f_0 in FP32 and the 8 moving
- * populations in FP16 as (f_l - E_l(href)) * 2^fp16_scale_log2, where
- * E_l(h) is the rest equilibrium (g h^2/6 on axes, g h^2/24 on diagonals);
- * the rest population absorbs the FP16 rounding so that the stored
- * populations of a site sum to its height. */
+ *
+ * Every form stores, and steps, the deviations d_l = f_l - E_l(href) of the
+ * populations from the rest equilibrium at the reference height href,
+ *   E_0(href) = href - 5 g href^2/6,  E_l(href) = g href^2/6 (axes), g href^2/24 (diagonals),
+ * so that h = href + sum_l d_l and h u = sum_l c_l d_l.  The step is the same
+ * map as on f (eq. "LBE"); only its rounding changes: FP32 resolves changes
+ * of h relative to |h - href| instead of |h|.  href = 0 stores f itself.  Pick
+ * href near the film height whose small changes matter (the mean of a nearly
+ * flat film); a drop on a precursor film is best served by href = h_*.  For
+ * TFLBM_FP32 and TFLBM_FP16S href is rounded to FP32 first.
+ *
+ * TFLBM_FP16S stores d_0 in FP32 and the 8 moving deviations in FP16 as
+ * d_l * 2^fp16_scale_log2; d_0 absorbs the FP16 rounding so that the stored
+ * populations of a site sum to its height.  FP16 keeps about 3 significant
+ * digits of d_l: changes of a population far below that (slow, small-amplitude
+ * dynamics) are rounded away and the film stagnates. */
 enum { TFLBM_FP64 = 0, TFLBM_FP32 = 1, TFLBM_FP16S = 2 };
 
 typedef struct tflbm_params {
@@ -76,7 +87,7 @@ typedef struct tflbm_params {
   double delta;            /* slip length, >= 0 */
   double ax, ay;           /* body acceleration: F = h (ax, ay) */
   double theta0;           /* uniform contact angle used when tflbm_init gets d_theta == NULL */
-  double fp16_href;        /* TFLBM_FP16S shift height href (>= 0) */
+  double href;             /* reference height of the stored deviations (>= 0; 0 stores f) */
 } tflbm_params;
 
 typedef struct tflbm_sim tflbm_sim; /* opaque; host memory only */

@@ -28,7 +28,7 @@ class Params(ctypes.Structure):
         ("n_exp", ctypes.c_int32), ("m_exp", ctypes.c_int32), ("fp16_scale_log2", ctypes.c_int32),
         ("tau", ctypes.c_double), ("gamma", ctypes.c_double), ("g", ctypes.c_double),
         ("hstar", ctypes.c_double), ("delta", ctypes.c_double), ("ax", ctypes.c_double),
-        ("ay", ctypes.c_double), ("theta0", ctypes.c_double), ("fp16_href", ctypes.c_double),
+        ("ay", ctypes.c_double), ("theta0", ctypes.c_double), ("href", ctypes.c_double),
     ]
 
 

@@ -86,9 +86,8 @@ StepArgs make_step_args(const tflbm_sim *s, int ns) {
   A.ay = s->p.ay;
   A.g = s->p.g;
   A.kappa0 = s->kappa0;
-  const double gh2 = s->p.g * s->p.fp16_href * s->p.fp16_href;
-  A.shift[0] = 0.0f;
-  for (int l = 1; l < 9; ++l) A.shift[l] = (float)((l & 1) ? gh2 / 6.0 : gh2 / 24.0);
+  // the FP32 forms step with href in FP32: take that value everywhere
+  A.href = s->p.prec == TFLBM_FP64 ? s->p.href : (double)(float)s->p.href;
   A.qscale = std::ldexp(1.0f, s->p.fp16_scale_log2);
   A.qinv = std::ldexp(1.0f, -s->p.fp16_scale_log2);
   return A;
@@ -127,7 +126,7 @@ void tflbm_default_params(tflbm_params *p) {
   p->hstar = 0.05;
   p->delta = 1.0;
   p->theta0 = 0.0;
-  p->fp16_href = 0.0;
+  p->href = 0.0;
 }
 
 static bool is_fin(double v) { return std::isfinite(v); }
@@ -145,7 +144,7 @@ int tflbm_check_params(const tflbm_params *p) {
   if (!is_fin(p->g) || !is_fin(p->ax) || !is_fin(p->ay) || !is_fin(p->theta0)) return TFLBM_EINVAL;
   if (!is_fin(p->hstar) || !(p->hstar > 0)) return TFLBM_EINVAL;
   if (!is_fin(p->delta) || p->delta < 0) return TFLBM_EINVAL;
-  if (!is_fin(p->fp16_href) || p->fp16_href < 0) return TFLBM_EINVAL;
+  if (!is_fin(p->href) || p->href < 0) return TFLBM_EINVAL;
   const double nu = (p->tau - 0.5) / 3.0;
   if (p->delta == 0.0 || 2.0 * nu / (p->delta * p->delta) >= 2.0) return TFLBM_EUNSTABLE;
   return TFLBM_OK;

@@ -78,7 +78,7 @@ struct StepArgs {
   int nstrips, H, ntiles, per_xcd;
   int n_exp, m_exp;
   double omega, gamma, nu, hstar, delta, ax, ay, g, kappa0;
-  float shift[9];         // FP16S: rest-equilibrium shift of each moving population
+  double href;            // reference height: stored d_l = f_l - E_l(href), h = href + sum d
   float qscale, qinv;     // FP16S: 2^s and 2^-s
 };
 
@@ -167,7 +167,8 @@ template <typename T> __device__ __forceinline__ T ipow(T x, int n) {
 }
 
 // ---- population storage ------------------------------------------------
-// Element of population l at (row y, stored column c), widened to T.
+// Stored deviation d_l = f_l - E_l(href) of population l at (row y, stored
+// column c), widened to T.
 template <int P>
 __device__ __forceinline__ typename Form<P>::T pop_at(const char *buf, int l, int y, int c, const StepArgs &A) {
   constexpr int B = Form<P>::B;
@@ -177,7 +178,7 @@ __device__ __forceinline__ typename Form<P>::T pop_at(const char *buf, int l, in
   else if constexpr (P == kF32) return ((const float *)rec)[pos];
   else {
     if (l == 0) return ((const float *)rec)[pos];
-    return A.shift[l] + __half2float(((const __half *)rec)[pos]) * A.qinv;
+    return __half2float(((const __half *)rec)[pos]) * A.qinv;
   }
 }
 

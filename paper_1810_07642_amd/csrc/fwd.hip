@@ -29,10 +29,10 @@
 
 namespace tflbm {
 
-// Loads the stored values of population l at the lane's columns of one row
-// (resource `row`); oe/o16 are the lane's byte offsets in a segment of the
-// working type (FP32 or FP64) and in an FP16 segment; the segment offset is a
-// compile-time immediate.
+// Loads the stored deviations d_l = f_l - E_l(href) of population l at the
+// lane's columns of one row (resource `row`); oe/o16 are the lane's byte
+// offsets in a segment of the working type (FP32 or FP64) and in an FP16
+// segment; the segment offset is a compile-time immediate.
 template <int P>
 __device__ __forceinline__ void load_raw(rsrc_t row, int l, const int *oe, const int *o16, bool vec,
                                          typename Form<P>::T *out, const StepArgs &A) {
@@ -60,14 +60,13 @@ __device__ __forceinline__ void load_raw(rsrc_t row, int l, const int *oe, const
         for (int v = 0; v < V; ++v) out[v] = ld_f32(row, oe[v] + seg);
       }
     } else {
-      const float s = A.shift[l];
       if (vec) {
         const __half2 q = ld_f16x2(row, o16[0] + seg);
-        out[0] = s + __low2float(q) * A.qinv;
-        out[1] = s + __high2float(q) * A.qinv;
+        out[0] = __low2float(q) * A.qinv;
+        out[1] = __high2float(q) * A.qinv;
       } else {
 #pragma unroll
-        for (int v = 0; v < V; ++v) out[v] = s + __half2float(ld_f16(row, o16[v] + seg)) * A.qinv;
+        for (int v = 0; v < V; ++v) out[v] = __half2float(ld_f16(row, o16[v] + seg)) * A.qinv;
       }
     }
   }
@@ -85,13 +84,15 @@ template <int P> struct Lane {
 
 // Step constants in the working type.
 template <typename T> struct Coef {
-  T omega, om1, nu, hstar, ax, ay, kap0, cA, cD, three_delta2, six_delta, mgam, mgam6, g6, g24, g56;
+  T omega, om1, nu, hstar, href, g, ax, ay, kap0, cA, cD, three_delta2, six_delta, mgam, mgam6;
   int n_exp, m_exp;
   __device__ explicit Coef(const StepArgs &A) {
     omega = (T)A.omega;
     om1 = (T)(1.0 - A.omega);
     nu = (T)A.nu;
     hstar = (T)A.hstar;
+    href = (T)A.href;
+    g = (T)A.g;
     ax = (T)A.ax;
     ay = (T)A.ay;
     kap0 = (T)A.kappa0;
@@ -101,9 +102,6 @@ template <typename T> struct Coef {
     six_delta = (T)(6.0 * A.delta);
     mgam = (T)(-A.gamma);
     mgam6 = (T)(-A.gamma / 6.0);
-    g6 = (T)(A.g / 6.0);
-    g24 = (T)(A.g / 24.0);
-    g56 = (T)(5.0 * A.g / 6.0);
     n_exp = A.n_exp;
     m_exp = A.m_exp;
   }
@@ -129,15 +127,19 @@ __device__ __forceinline__ void shift_x(int l, const T *in, T *out) {
 }
 
 // One time step applied row by row to a marching strip.  ingest(k, ...)
-// takes the pre-collision populations of the stage's k-th row r and forms
-// h(r); finish(k, ...) forms the film pressure of row r-1 and, for k >= 4,
-// the post-collision populations of row r-2 (eqs. "LBE", "equilibria",
-// "force", "pfilm", "disjoiningP", "forcefric", "alphafric", "derivative",
-// "n_laplace").  The populations of rows r-1 and r-2 wait in two LDS slots.
+// takes the pre-collision deviations d_l = f_l - E_l(href) of the stage's
+// k-th row r and forms dh = h - href = sum d; finish(k, ...) forms the film
+// pressure of row r-1 and, for k >= 4, the post-collision deviations of row
+// r-2 (eqs. "LBE", "equilibria", "force", "pfilm", "disjoiningP",
+// "forcefric", "alphafric", "derivative", "n_laplace").  The populations of
+// rows r-1 and r-2 wait in two LDS slots.  The shift by E_l(href) is constant,
+// has zero momentum and is a fixed point of the collision at rest, so the
+// step on d is the step on f; only small changes of a film near href keep
+// more significant digits.
 template <int P, bool KF> struct Stage {
   using T = typename Form<P>::T;
   static constexpr int V = Form<P>::V;
-  T h0[V + 2], h1[V + 2], h2[V + 2];  // h of rows r, r-1, r-2 with the left/right neighbours
+  T h0[V + 2], h1[V + 2], h2[V + 2];  // dh of rows r, r-1, r-2 with the left/right neighbours
   T p1[V + 2], p2[V + 2], p3[V + 2];  // p of rows r-1, r-2, r-3
   T kn[V], kr[V];                     // kappa of rows r and r-1
   T (*hist)[9][64 * V];
@@ -200,9 +202,9 @@ template <int P, bool KF> struct Stage {
         even += h0[v];
         even += h2[v];
         even += h2[v + 2];
-        const T hc = h1[v + 1];
-        // 6 lap = 4 sum_axes + sum_diagonals - 20 h
-        const T lap6 = madd(T(-20), hc, madd(T(4), odd, even));
+        const T hc = C.href + h1[v + 1];
+        // 6 lap h = 6 lap dh = 4 sum_axes + sum_diagonals - 20 dh
+        const T lap6 = madd(T(-20), h1[v + 1], madd(T(4), odd, even));
         const T phi = disjoining(C.hstar * recip(hc), C.n_exp, C.m_exp);
         const T kap = KF ? kr[v] : C.kap0;
         p1[v + 1] = madd(C.mgam6, lap6, C.mgam * kap * phi);
@@ -218,7 +220,8 @@ template <int P, bool KF> struct Stage {
         const T gx = madd(C.cA, p2[v + 2] - p2[v], C.cD * ((p1[v + 2] - p1[v]) + (p3[v + 2] - p3[v])));
         const T gy = madd(C.cA, p1[v + 1] - p3[v + 1], C.cD * ((p1[v + 2] - p3[v + 2]) + (p1[v] - p3[v])));
 
-        const T h = h2[1 + v];
+        const T dh = h2[1 + v];
+        const T h = C.href + dh;
         T jx = f2[1][v];
         jx += f2[2][v];
         jx -= f2[4][v];
@@ -240,22 +243,23 @@ template <int P, bool KF> struct Stage {
         const T Fx = madd(h, C.ax - gx, -fric * ux);
         const T Fy = madd(h, C.ay - gy, -fric * uy);
 
-        // equilibrium (lattice speed 1 in the printed denominators) as h times
-        // a polynomial in c.u:
-        //   rest: h (1 - 5 g h/6 - 2 u^2/3)
-        //   axes: h ((g h - u^2)/6 + c.u/3 + (c.u)^2/2)
-        //   diagonals: h ((g h - u^2)/24 + c.u/12 + (c.u)^2/8)
-        // BGK with forcing: f + omega (feq - f) + 3 w_l c_l.F
+        // equilibrium (lattice speed 1 in the printed denominators) minus the
+        // stored shift E_l(href, 0), with q = g (h^2 - href^2) = g dh (h + href):
+        //   rest: dh - 5 q/6 - 2 h u^2/3
+        //   axes: q/6 + h ((c.u)/3 + (c.u)^2/2 - u^2/6)
+        //   diagonals: q/24 + h ((c.u)/12 + (c.u)^2/8 - u^2/24)
+        // BGK with forcing: d + omega (deq - d) + 3 w_l c_l.F
         const T usq = madd(ux, ux, uy * uy);
-        const T a1 = madd(C.g6, h, usq * T(-1.0 / 6.0));
-        const T a2 = madd(C.g24, h, usq * T(-1.0 / 24.0));
+        const T a1 = usq * T(-1.0 / 6.0);
+        const T a2 = usq * T(-1.0 / 24.0);
         const T hom = h * C.omega;
+        const T G = C.omega * (C.g * dh * (h + C.href));  // omega q
 #pragma unroll
         for (int l = 0; l < 9; ++l) {
           T poly, src;
           if (l == 0) {
-            poly = madd(-C.g56, h, madd(usq, T(-2.0 / 3.0), T(1)));
-            src = T(0);
+            poly = usq * T(-2.0 / 3.0);
+            src = madd(G, T(-5.0 / 6.0), C.omega * dh);
           } else {
             const int cx = kCx[l], cy = kCy[l];
             const T cu = cx == 0 ? (cy > 0 ? uy : -uy)
@@ -266,16 +270,16 @@ template <int P, bool KF> struct Stage {
                                             : (cx > 0 ? (cy > 0 ? Fx + Fy : Fx - Fy) : (cy > 0 ? Fy - Fx : -Fx - Fy)));
             if (l & 1) {
               poly = madd(cu, madd(cu, T(0.5), T(1.0 / 3.0)), a1);
-              src = cF * T(1.0 / 3.0);
+              src = madd(G, T(1.0 / 6.0), cF * T(1.0 / 3.0));
             } else {
               poly = madd(cu, madd(cu, T(0.125), T(1.0 / 12.0)), a2);
-              src = cF * T(1.0 / 12.0);
+              src = madd(G, T(1.0 / 24.0), cF * T(1.0 / 12.0));
             }
           }
-          // f + omega (h poly - f) + src = (1 - omega) f + (h omega) poly + src
+          // d + omega (h poly + q-term - d) + forcing = (1 - omega) d + (h omega) poly + src
           post[l][v] = madd(C.om1, f2[l][v], madd(hom, poly, src));
         }
-        hv[v] = h;
+        hv[v] = dh;
         jxv[v] = jx;
         jyv[v] = jy;
         if (L.out[v] && !(h > T(0) && h < T(INFINITY))) bad = 1;
@@ -292,8 +296,8 @@ template <int P, bool KF> struct Stage {
   }
 };
 
-// Stores the post-collision populations of row y (values at the lane's own
-// columns) into stored column x of rows y + c_ly.
+// Stores the post-collision deviations of row y (values at the lane's own
+// columns, hv = dh of the row) into stored column x of rows y + c_ly.
 template <int P>
 __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typename Form<P>::T (&post)[9][Form<P>::V],
                                           const typename Form<P>::T (&hv)[Form<P>::V], const Lane<P> &L, int x0,
@@ -317,12 +321,11 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
     for (int l = 1; l < 9; ++l) {
       const rsrc_t rd = rowD[kCy[l] + 1];
       const int seg = seg_offset<P>(l);
-      const float s = A.shift[l];
       __half q[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        q[v] = __float2half_rn((post[l][v] - s) * A.qscale);
-        rest[v] -= s + __half2float(q[v]) * A.qinv;  // rest population absorbs the rounding
+        q[v] = __float2half_rn(post[l][v] * A.qscale);
+        rest[v] -= __half2float(q[v]) * A.qinv;  // rest deviation absorbs the rounding
       }
       if (pair) {
         st_f16x2(rd, L.o16[0] + seg, q[0], q[1]);
@@ -369,9 +372,9 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
   }
 }
 
-// FP16S storage round trip of one row of post-collision values (what a store
-// followed by a load would give): moving populations rounded to FP16 in the
-// shifted, scaled form, rest population h - sum of the decoded moving ones.
+// FP16S storage round trip of one row of post-collision deviations (what a
+// store followed by a load would give): moving deviations rounded to FP16 in
+// the scaled form, rest deviation dh - sum of the decoded moving ones.
 template <int V>
 __device__ __forceinline__ void fp16s_roundtrip(float (&post)[9][V], const float (&hv)[V], const StepArgs &A) {
 #pragma unroll
@@ -379,9 +382,8 @@ __device__ __forceinline__ void fp16s_roundtrip(float (&post)[9][V], const float
     float rest = hv[v];
 #pragma unroll
     for (int l = 1; l < 9; ++l) {
-      const float s = A.shift[l];
-      const __half q = __float2half_rn((post[l][v] - s) * A.qscale);
-      const float d = s + __half2float(q) * A.qinv;
+      const __half q = __float2half_rn(post[l][v] * A.qscale);
+      const float d = __half2float(q) * A.qinv;
       rest -= d;
       post[l][v] = d;
     }
@@ -487,7 +489,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
 #pragma unroll
           for (int v = 0; v < V; ++v) {
             if (L.out[v]) {
-              st_t(c0, L.col[v] * ES, hv[v]);
+              st_t(c0, L.col[v] * ES, C.href + hv[v]);
               st_t(c1, L.col[v] * ES, jxv[v]);
               st_t(c2, L.col[v] * ES, jyv[v]);
             }
@@ -545,7 +547,9 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
 
 // ---- initial populations and kappa ------------------------------------------
 // f_l = f_l^eq(h0, u = 0): h0 - 5 g h0^2/6 (rest), g h0^2/6 (axes), g h0^2/24
-// (diagonals); kappa = (1 - cos theta)(n - 1)(m - 1)/((n - m) h_*) (Sec. II).
+// (diagonals), stored as d_l = f_l - E_l(href), i.e. with dh = h0 - href and
+// q = g dh (h0 + href): dh - 5 q/6, q/6, q/24; kappa = (1 - cos theta)(n - 1)
+// (m - 1)/((n - m) h_*) (Sec. II).
 template <int P> __device__ __forceinline__ char *pop_ptr(char *buf, int l, int y, int c, const StepArgs &A) {
   constexpr int B = Form<P>::B;
   const int blk = c / B, pos = c - blk * B;
@@ -562,21 +566,21 @@ __global__ void init_kernel(StepArgs A, const double *h0, const double *theta, d
   if (x >= A.nx) return;
   const double h = h0[(size_t)y * A.nx + x];
   if (!(h > 0.0 && h < INFINITY)) atomicOr(A.flag, 1);
-  const double gh2 = A.g * h * h;
+  const double dh = h - A.href;
+  const double q = A.g * dh * (h + A.href);
   double e[9];
-  e[0] = h - gh2 * (5.0 / 6.0);
-  for (int l = 1; l < 9; ++l) e[l] = (l & 1) ? gh2 * (1.0 / 6.0) : gh2 * (1.0 / 24.0);
+  e[0] = dh - q * (5.0 / 6.0);
+  for (int l = 1; l < 9; ++l) e[l] = (l & 1) ? q * (1.0 / 6.0) : q * (1.0 / 24.0);
   if constexpr (P == kF64 || P == kF32) {
     for (int l = 0; l < 9; ++l) *(T *)pop_ptr<P>(A.dst, l, y, wrap(x - kCx[l], A.nx), A) = (T)e[l];
   } else {
-    float sumdq = 0.f;
+    double sumd = 0.0;
     for (int l = 1; l < 9; ++l) {
-      const float s = A.shift[l];
-      const __half q = __float2half_rn(((float)e[l] - s) * A.qscale);
-      *(__half *)pop_ptr<P>(A.dst, l, y, wrap(x - kCx[l], A.nx), A) = q;
-      sumdq += s + __half2float(q) * A.qinv;
+      const __half dq = __float2half_rn((float)e[l] * A.qscale);
+      *(__half *)pop_ptr<P>(A.dst, l, y, wrap(x - kCx[l], A.nx), A) = dq;
+      sumd += (double)(__half2float(dq) * A.qinv);
     }
-    *(float *)pop_ptr<P>(A.dst, 0, y, x, A) = (float)h - sumdq;
+    *(float *)pop_ptr<P>(A.dst, 0, y, x, A) = (float)(dh - sumd);
   }
   if (theta != nullptr) {
     const double th = theta[(size_t)y * A.nx + x];
@@ -584,7 +588,7 @@ __global__ void init_kernel(StepArgs A, const double *h0, const double *theta, d
   }
 }
 
-// ---- readout: h and u = j/h in FP64 from the stored populations --------------
+// ---- readout: h = href + sum d and u = j/h in FP64 from the stored deviations --
 template <int P>
 __global__ void read_kernel(StepArgs A, double *hout, double *uxo, double *uyo) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -592,8 +596,9 @@ __global__ void read_kernel(StepArgs A, double *hout, double *uxo, double *uyo) 
   if (x >= A.nx) return;
   double f[9];
   for (int l = 0; l < 9; ++l) f[l] = (double)pop_at<P>(A.src, l, y, wrap(x - kCx[l], A.nx), A);
-  double h = f[0];
-  for (int l = 1; l < 9; ++l) h += f[l];
+  double dh = f[0];
+  for (int l = 1; l < 9; ++l) dh += f[l];
+  const double h = A.href + dh;
   const double jx = f[1] + f[2] - f[4] - f[5] - f[6] + f[8];
   const double jy = f[2] + f[3] + f[4] - f[6] - f[7] - f[8];
   const size_t od = (size_t)y * A.nx + x;
@@ -603,6 +608,7 @@ __global__ void read_kernel(StepArgs A, double *hout, double *uxo, double *uyo) 
 }
 
 // ---- mass: deterministic two-pass FP64 reduction ------------------------------
+// sum over sites of sum_l d_l, plus nx ny href.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -626,14 +632,14 @@ __global__ __launch_bounds__(256) void mass_partial_kernel(StepArgs A, double *p
   if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ __launch_bounds__(256) void mass_final_kernel(const double *partial, int np, double *out) {
+__global__ __launch_bounds__(256) void mass_final_kernel(const double *partial, int np, double base, double *out) {
   __shared__ double red[4];
   double acc = 0.0;
   for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partial[i];
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) out[0] = base + ((red[0] + red[1]) + (red[2] + red[3]));
 }
 
 // ---- launchers -----------------------------------------------------------------
@@ -725,7 +731,7 @@ hipError_t launch_mass(int prec, const StepArgs &A, double *partial, int np, dou
     case kF32: mass_partial_kernel<kF32><<<np, 256, 0, s>>>(A, partial); break;
     default: mass_partial_kernel<kF16S><<<np, 256, 0, s>>>(A, partial); break;
   }
-  mass_final_kernel<<<1, 256, 0, s>>>(partial, np, out);
+  mass_final_kernel<<<1, 256, 0, s>>>(partial, np, (double)A.nx * (double)A.ny * A.href, out);
   return hipGetLastError();
 }
 

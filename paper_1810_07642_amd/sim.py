@@ -13,7 +13,7 @@ import torch
 from . import _lib
 
 PARAM_KEYS = ("tau", "gamma", "g", "hstar", "n", "m", "delta", "ax", "ay", "theta0",
-              "fp16_href", "fp16_scale_log2")
+              "href", "fp16_scale_log2")
 
 
 def _stream(device):

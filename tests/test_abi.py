@@ -47,7 +47,7 @@ def test_struct_layout_matches_header(lib):
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("ny", -3), ("prec", 3), ("tau", 0.5), ("tau", float("nan")), ("hstar", 0.0),
     ("gamma", -1.0), ("delta", -0.1), ("n_exp", 3), ("m_exp", 0), ("fp16_scale_log2", 30),
-    ("g", float("inf")), ("fp16_href", -1.0),
+    ("g", float("inf")), ("href", -1.0),
 ])
 def test_invalid_parameters_rejected(lib, field, value):
     p = params(lib, **{field: value})

@@ -80,6 +80,46 @@ def test_fp32_matches_oracle(case):
     assert err <= fp32_tol(steps)
 
 
+@pytest.mark.parametrize("case", [0, 2, 3])
+def test_reference_height_fp64_and_fp32_match_oracle(case):
+    """Storage as deviations from E_l(href) is the same map: FP64 within
+    1e-12, FP32 within its bound, mass to 1e-13 (FP64), for href inside the
+    range of h0 (0.3 .. 0.6) and above it."""
+    ny, nx, steps, p = CASES[case]
+    h0, th = random_case(ny, nx, 100 + case)
+    ho, uxo, uyo, mo = oracle_run(p, h0, th, steps)
+    for href in (0.45, 0.8):
+        banner(f"href {href} parity case {case}")
+        hg, uxg, uyg, mg = gpu_run(p, h0, th, steps, "fp64", href=href)
+        assert max_rel(hg, ho) <= TOL64
+        assert max_rel(uxg, uxo) <= TOL64 * 10 or float((uxg - uxo).abs().max()) < 1e-18
+        assert abs(mg - mo) <= 1e-13 * abs(mo)
+        hg, _, _, _ = gpu_run(p, h0, th, steps, "fp32", href=href)
+        assert max_rel(hg, ho) <= fp32_tol(steps)
+
+
+def test_reference_height_resolves_small_amplitude_film_in_fp32():
+    """Hanging film h0 = 1 + 1e-4 s(x) (s: seeded noise keeping modes up to 8
+    of 32), g = -1e-4, 2000 steps.  With href = 1 the FP32 step rounds values
+    of the size of h - 1, so its error relative to the amplitude obeys the
+    FP32 bound; with href = 0 it rounds values of the size of h and the error
+    is at least ten times larger."""
+    banner("fp32 small-amplitude film, href 1 vs 0")
+    n, steps = 64, 2000
+    p = dict(tau=1.0, gamma=0.01, g=-1e-4, hstar=0.05, delta=0.5)
+    h0 = 1.0 + 1e-4 * inputs.lowpass(inputs.uniform_noise(n, n, 21), 8)
+    th = torch.zeros((n, n), dtype=torch.float64)
+    ho, _, _, _ = oracle_run(p, h0, th, steps)
+    amp = float((ho - 1.0).abs().max())
+    errs = {}
+    for href in (1.0, 0.0):
+        hg, _, _, _ = gpu_run(p, h0, th, steps, "fp32", href=href)
+        errs[href] = float((hg - ho).abs().max()) / amp
+    print(f"max|dh| / max|h - 1|: href 1 -> {errs[1.0]:.3e}, href 0 -> {errs[0.0]:.3e}")
+    assert errs[1.0] <= fp32_tol(steps)
+    assert errs[0.0] >= 10 * errs[1.0]
+
+
 @pytest.mark.parametrize("case", [0, 1, 2, 5])
 def test_fp16s_matches_oracle(case):
     """FP16-shifted storage: the moving populations carry a relative error of
@@ -172,15 +212,16 @@ def test_checkpoint_restore_is_bitwise_and_runs_are_deterministic():
         assert torch.equal(c.height().cpu(), ha)
 
 
+@pytest.mark.parametrize("href", [0.0, 0.45])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
-def test_fused_steps_equal_single_steps_bitwise(prec):
+def test_fused_steps_equal_single_steps_bitwise(prec, href):
     """Two time steps fused in one pass give the same bits as two passes of
     one step (same arithmetic, intermediate rows kept on chip), on ragged,
     odd and degenerate grids, with an odd step count (fused pairs plus one
     single step)."""
     import os
     from paper_1810_07642_amd import Sim
-    p = dict(tau=0.9, gamma=0.01, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5, ay=-1e-5)
+    p = dict(tau=0.9, gamma=0.01, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5, ay=-1e-5, href=href)
     for (ny, nx) in [(70, 150), (23, 37), (1, 1), (6, 300), (130, 97)]:
         h0, th = random_case(ny, nx, 41)
         states = []
@@ -194,4 +235,4 @@ def test_fused_steps_equal_single_steps_bitwise(prec):
             sim.check()
             states.append((sim.state_save().cpu(),) + tuple(t.cpu() for t in sim.read()))
         for a, b in zip(states[0], states[1]):
-            assert torch.equal(a, b), (prec, ny, nx)
+            assert torch.equal(a, b), (prec, href, ny, nx)

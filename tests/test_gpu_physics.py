@@ -1,0 +1,86 @@
+"""Physics of the hanging-film (Rayleigh-Taylor) workload on the GPU path.
+
+512 x 512 periodic film h0 = 1 + 1e-3 U(-1, 1) (seed 1), g = -1e-4 (destabilising),
+gamma = 0.01, tau = 1, delta = 0.5, no wetting term (Sec. III A), 50000 steps.  The noise
+keeps Fourier modes up to 64 of 256: the checkerboard mode of the scheme grows by
+2.7e-4 per step for this g (test_checkerboard_mode_unstable_for_negative_gravity) and from
+unfiltered 1e-3 noise drives h to zero near step 34000.  Both forms store deviations from
+the rest equilibrium at href = 1 (FP32 with href = 0 cannot resolve the 1e-10 per-step
+changes of h near 1, and its rounding seeds the unstable band).  In the
+linear regime every Fourier mode of h grows at the rate of the slowest eigenvalue of the
+one-step propagator of the linearised scheme (tests/physics.py, pinned on the CPU against
+the oracle and against the thin-film law eq. "RTgrowth" with its discrete corrections).
+The rate measured per mode between t1 = 1000 (fast modes gone) and t2 = 50000 must match it.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import banner
+from paper_1810_07642_amd import inputs
+from physics import fourier_step, lubrication_growth
+
+pytestmark = pytest.mark.gpu
+
+N, T1, T2 = 512, 1000, 50000
+
+
+def growth_rates(prec):
+    from paper_1810_07642_amd import Sim
+    p, h0, th = inputs.rayleigh_taylor(n=N, max_mode=64)
+    sim = Sim(N, N, prec, href=1.0, **p).init(h0, th)
+    sim.step(T1)
+    h1 = sim.height().cpu()
+    sim.step(T2 - T1)
+    h2 = sim.height().cpu()
+    sim.check()
+    a1 = torch.fft.fft2(h1 - h1.mean()).abs()
+    a2 = torch.fft.fft2(h2 - h2.mean()).abs()
+    return p, torch.log(a2 / a1) / (T2 - T1), h2
+
+
+def lb_rate(kx, ky, p):
+    A = fourier_step(kx, ky, 1.0, p["tau"], p["gamma"], p["g"], 0.0, p["hstar"], p["n"], p["m"], p["delta"])
+    ev = np.linalg.eigvals(A)
+    return math.log(abs(ev[np.argmin(np.abs(np.abs(ev) - 1.0))]))
+
+
+def test_rayleigh_taylor_mode_growth_fp64_and_fp32():
+    banner("RT 512^2 x 50000, fp64 and fp32")
+    res = {}
+    for prec in ("fp64", "fp32"):
+        p, sig, h = growth_rates(prec)
+        res[prec] = (sig, h)
+    p = inputs.rayleigh_taylor(n=8)[0]
+    nu = (p["tau"] - 0.5) / 3.0
+    rows = []
+    for my in range(0, 9):
+        for mx in range(0, 9):
+            n = math.hypot(mx, my)
+            if not (1.0 <= n <= 12.0):
+                continue
+            kx, ky = 2 * math.pi * mx / N, 2 * math.pi * my / N
+            k = math.hypot(kx, ky)
+            expect = lb_rate(kx, ky, p)
+            lub = lubrication_growth(k, 1.0, abs(p["g"]), p["gamma"], nu, p["delta"])
+            got64 = float(res["fp64"][0][my, mx])
+            got32 = float(res["fp32"][0][my, mx])
+            rows.append((n, mx, my, expect, lub, got64, got32))
+    print("mode   mx my  sigma_LB     sigma_lub    measured64   measured32")
+    for r in sorted(rows):
+        print("%5.2f %3d %2d %+.4e %+.4e %+.4e %+.4e" % r)
+    h64, h32 = res["fp64"][1], res["fp32"][1]
+    print(f"fp32 vs fp64 final h: max |dh| = {float((h32 - h64).abs().max()):.3e}", flush=True)
+    for n, mx, my, expect, lub, got64, got32 in rows:
+        # the linear eigenvalue, to 3% of the rate (plus the O(1e-3) amplitude nonlinearity)
+        assert abs(got64 - expect) <= 0.03 * abs(expect) + 2e-8, (mx, my, got64, expect)
+        assert abs(got32 - got64) <= 0.03 * abs(expect) + 2e-8, (mx, my, got32, got64)
+    # sign structure of eq. "RTgrowth": growth below the neutral wavenumber, decay above
+    kc_modes = math.sqrt(abs(p["g"]) / p["gamma"]) * N / (2 * math.pi)
+    for n, mx, my, expect, lub, got64, _ in rows:
+        if n < 0.9 * kc_modes:
+            assert got64 > 0, (mx, my, got64)
+        if n > 1.05 * kc_modes:
+            assert got64 < 0, (mx, my, got64)
