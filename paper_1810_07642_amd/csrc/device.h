@@ -130,9 +130,24 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
-// Value of `v` held by lane - 1 (own value on lane 0) / lane + 1 (own value on lane 63).
-template <typename T> __device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1); }
-template <typename T> __device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1); }
+// Value of `v` held by lane - 1 (own value on lane 0) / lane + 1 (own value on
+// lane 63): DPP whole-wavefront shifts by one lane (wave_shr:1 = 0x138,
+// wave_shl:1 = 0x130), VALU moves that the compiler can fold into the
+// consuming instruction; a lane without a source keeps `old` = its own value.
+__device__ __forceinline__ int wave_shr1(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int wave_shl1(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(wave_shr1(__float_as_int(v))); }
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(wave_shl1(__float_as_int(v))); }
+__device__ __forceinline__ double from_left(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = wave_shr1((int)(b & 0xffffffffll)), hi = wave_shr1((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = wave_shl1((int)(b & 0xffffffffll)), hi = wave_shl1((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 // a * b + c: fused for FP32 (one rounding), two roundings for FP64 so that the
 // FP64 step keeps the unfused arithmetic of its reference.

@@ -80,7 +80,27 @@ template <int P> struct Lane {
   bool out[V];        // the column is an output of this strip
   bool vec;           // the column pair lies in one record, 8-byte aligned
   bool vecp;          // the column pair is contiguous and aligned in a plane array
+  bool allvec;        // wave-uniform: vec on every lane
+  bool allvecp;       // wave-uniform: vecp on every lane
+  bool pair;          // all V columns are outputs and vec holds
+  bool fast_store;    // wave-uniform: every lane has all or none of its columns as outputs, with vec
 };
+
+// Loads the stored deviations of all nine populations of one row.  Strips
+// whose lanes all hold aligned column pairs (every strip of a lattice whose
+// width is a multiple of the record size, and all interior strips otherwise)
+// take the wave-uniform vector path with no per-lane branches.
+template <int P>
+__device__ __forceinline__ void load_row(rsrc_t row, const Lane<P> &L, typename Form<P>::T (&out)[9][Form<P>::V],
+                                         const StepArgs &A) {
+  if (L.allvec) {
+#pragma unroll
+    for (int l = 0; l < 9; ++l) load_raw<P>(row, l, L.oe, L.o16, true, out[l], A);
+  } else {
+#pragma unroll
+    for (int l = 0; l < 9; ++l) load_raw<P>(row, l, L.oe, L.o16, L.vec, out[l], A);
+  }
+}
 
 // Step constants in the working type.
 template <typename T> struct Coef {
@@ -162,7 +182,11 @@ template <int P, bool KF> struct Stage {
       const uint32_t prb = (uint32_t)(A.ldx * sizeof(T));
       const rsrc_t krow = make_rsrc((const char *)A.kfield + (size_t)ry * prb, prb);
       if constexpr (V == 2) {
-        if (L.vecp) {
+        if (L.allvecp) {
+          const float2 kv = ld_f32x2(krow, L.col[0] * 4);
+          kn[0] = kv.x;
+          kn[1] = kv.y;
+        } else if (L.vecp) {
           const float2 kv = ld_f32x2(krow, L.col[0] * 4);
           kn[0] = kv.x;
           kn[1] = kv.y;
@@ -312,35 +336,46 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
   const int yS = (y == 0) ? ny - 1 : y - 1;
   const rsrc_t rowD[3] = {make_rsrc(A.dst + yS * rowB, (uint32_t)rowB), make_rsrc(A.dst + y * rowB, (uint32_t)rowB),
                           make_rsrc(A.dst + yN * rowB, (uint32_t)rowB)};  // indexed by c_ly + 1
-  const bool pair = L.out[0] && L.out[V - 1] && L.vec;
+  const bool pair = L.pair;
   if constexpr (P == kF16S) {
     float rest[V];
+    __half q[9][V];
 #pragma unroll
     for (int v = 0; v < V; ++v) rest[v] = hv[v];
 #pragma unroll
     for (int l = 1; l < 9; ++l) {
-      const rsrc_t rd = rowD[kCy[l] + 1];
-      const int seg = seg_offset<P>(l);
-      __half q[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        q[v] = __float2half_rn(post[l][v] * A.qscale);
-        rest[v] -= __half2float(q[v]) * A.qinv;  // rest deviation absorbs the rounding
+        q[l][v] = __float2half_rn(post[l][v] * A.qscale);
+        rest[v] -= __half2float(q[l][v]) * A.qinv;  // rest deviation absorbs the rounding
+      }
+    }
+    if (L.fast_store) {
+      if (pair) {
+#pragma unroll
+        for (int l = 1; l < 9; ++l) st_f16x2(rowD[kCy[l] + 1], L.o16[0] + seg_offset<P>(l), q[l][0], q[l][1]);
+        st_f32x2(rowD[1], L.oe[0], rest[0], rest[1]);
+      }
+    } else {
+#pragma unroll
+      for (int l = 1; l < 9; ++l) {
+        const rsrc_t rd = rowD[kCy[l] + 1];
+        const int seg = seg_offset<P>(l);
+        if (pair) {
+          st_f16x2(rd, L.o16[0] + seg, q[l][0], q[l][1]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            if (L.out[v]) st_f16(rd, L.o16[v] + seg, q[l][v]);
+        }
       }
       if (pair) {
-        st_f16x2(rd, L.o16[0] + seg, q[0], q[1]);
+        st_f32x2(rowD[1], L.oe[0], rest[0], rest[1]);
       } else {
 #pragma unroll
         for (int v = 0; v < V; ++v)
-          if (L.out[v]) st_f16(rd, L.o16[v] + seg, q[v]);
+          if (L.out[v]) st_f32(rowD[1], L.oe[v], rest[v]);
       }
-    }
-    if (pair) {
-      st_f32x2(rowD[1], L.oe[0], rest[0], rest[1]);
-    } else {
-#pragma unroll
-      for (int v = 0; v < V; ++v)
-        if (L.out[v]) st_f32(rowD[1], L.oe[v], rest[v]);
     }
     // fill the 64-byte pads after the c_ly = +1 and -1 groups of a full
     // record so that its lines are written whole
@@ -350,6 +385,16 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
         const int rec = (x0 / B) * RB;
         st_f32(rowD[2], rec + 1344 + 4 * q16, 0.f);
         st_f32(rowD[0], rec + 1984 + 4 * q16, 0.f);
+      }
+    }
+  } else if (L.fast_store) {
+    // every lane stores all of its columns or none: one masked region
+    if (pair) {
+#pragma unroll
+      for (int l = 0; l < 9; ++l) {
+        const rsrc_t rd = rowD[kCy[l] + 1];
+        if constexpr (P == kF64) st_f64(rd, L.oe[0] + seg_offset<P>(l), post[l][0]);
+        else st_f32x2(rd, L.oe[0] + seg_offset<P>(l), post[l][0], post[l][1]);
       }
     }
   } else {
@@ -439,6 +484,10 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
     L.vec = (L.col[1] == L.col[0] + 1) && (L.col[0] / B == L.col[1] / B) && ((L.col[0] & 1) == 0);
     L.vecp = (L.col[1] == L.col[0] + 1) && ((L.col[0] & 1) == 0);
   }
+  L.pair = L.out[0] && L.out[V - 1] && L.vec;
+  L.allvec = __all(L.vec);
+  L.allvecp = __all(L.vecp);
+  L.fast_store = __all(L.pair || (!L.out[0] && !L.out[V - 1]));
   const Coef<T> C(A);
 
   Stage<P, KF> S0;
@@ -457,12 +506,10 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   T fa[9][V], fb[9][V];  // stored values of rows r (being consumed) and r + 1
   int ry = wrap(y0 - HALO, ny);                          // row r of stage 0
   int rpre = ry + 2 >= ny ? (ry + 2) % ny : ry + 2;      // row r + 2
-#pragma unroll
-  for (int l = 0; l < 9; ++l) load_raw<P>(rsrc_src(ry), l, L.oe, L.o16, L.vec, fa[l], A);
+  load_row<P>(rsrc_src(ry), L, fa, A);
   if (K > 1) {
     const int r1 = ry + 1 == ny ? 0 : ry + 1;
-#pragma unroll
-    for (int l = 0; l < 9; ++l) load_raw<P>(rsrc_src(r1), l, L.oe, L.o16, L.vec, fb[l], A);
+    load_row<P>(rsrc_src(r1), L, fb, A);
   }
 
   auto iteration = [&](int k, T(&cur)[9][V]) {
@@ -471,10 +518,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
     for (int l = 0; l < 9; ++l) shift_x<T, V>(l, cur[l], f[l]);
     S0.ingest(k, ry, f, f2, L, A, lane);
     // prefetch row r + 2 into the registers just freed
-    if (k + 2 < K) {
-#pragma unroll
-      for (int l = 0; l < 9; ++l) load_raw<P>(rsrc_src(rpre), l, L.oe, L.o16, L.vec, cur[l], A);
-    }
+    if (k + 2 < K) load_row<P>(rsrc_src(rpre), L, cur, A);
     T post[9][V], hv[V], jxv[V], jyv[V];
     if (S0.finish(k, f2, post, hv, jxv, jyv, C, L, bad)) {
       const int q = y0 - HALO + k - 2;  // row of the post-collision values (unwrapped)
