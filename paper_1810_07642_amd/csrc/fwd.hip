@@ -160,7 +160,10 @@ template <int P, bool KF> struct Stage {
   using T = typename Form<P>::T;
   static constexpr int V = Form<P>::V;
   T h0[V + 2], h1[V + 2], h2[V + 2];  // dh of rows r, r-1, r-2 with the left/right neighbours
-  T p1[V + 2], p2[V + 2], p3[V + 2];  // p of rows r-1, r-2, r-3
+  // per row of p: x difference p(x+1) - p(x-1) and the x-smoothed value
+  // cA p(x) + cD (p(x-1) + p(x+1)), of rows r-1, r-2, r-3
+  T dx1[V], dx2[V], dx3[V];
+  T sm1[V], sm2[V], sm3[V];
   T kn[V], kr[V];                     // kappa of rows r and r-1
   T (*hist)[9][64 * V];
 
@@ -216,6 +219,7 @@ template <int P, bool KF> struct Stage {
                                          T (&jyv)[V], const Coef<T> &C, const Lane<P> &L, int &bad) {
     if (k >= 2) {
       // film pressure of row r-1: p = -gamma (lap h + kappa phi(h))
+      T pc[V + 2];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         T odd = h1[v + 2];
@@ -231,33 +235,31 @@ template <int P, bool KF> struct Stage {
         const T lap6 = madd(T(-20), h1[v + 1], madd(T(4), odd, even));
         const T phi = disjoining(C.hstar * recip(hc), C.n_exp, C.m_exp);
         const T kap = KF ? kr[v] : C.kap0;
-        p1[v + 1] = madd(C.mgam6, lap6, C.mgam * kap * phi);
+        pc[v + 1] = madd(C.mgam6, lap6, C.mgam * kap * phi);
       }
-      p1[0] = from_left(p1[V]);
-      p1[V + 1] = from_right(p1[1]);
+      pc[0] = from_left(pc[V]);
+      pc[V + 1] = from_right(pc[1]);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        dx1[v] = pc[v + 2] - pc[v];
+        sm1[v] = madd(C.cA, pc[v + 1], C.cD * (pc[v] + pc[v + 2]));
+      }
     }
     const bool emit = k >= 4;
     if (emit) {
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         // isotropic gradient of p: axis weight 1/3, diagonal 1/12
-        const T gx = madd(C.cA, p2[v + 2] - p2[v], C.cD * ((p1[v + 2] - p1[v]) + (p3[v + 2] - p3[v])));
-        const T gy = madd(C.cA, p1[v + 1] - p3[v + 1], C.cD * ((p1[v + 2] - p3[v + 2]) + (p1[v] - p3[v])));
+        const T gx = madd(C.cA, dx2[v], C.cD * (dx1[v] + dx3[v]));
+        const T gy = sm1[v] - sm3[v];
 
         const T dh = h2[1 + v];
         const T h = C.href + dh;
-        T jx = f2[1][v];
-        jx += f2[2][v];
-        jx -= f2[4][v];
-        jx -= f2[5][v];
-        jx -= f2[6][v];
-        jx += f2[8][v];
-        T jy = f2[2][v];
-        jy += f2[3][v];
-        jy += f2[4][v];
-        jy -= f2[6][v];
-        jy -= f2[7][v];
-        jy -= f2[8][v];
+        // j = sum_l c_l d_l through the differences of opposite populations
+        const T d15 = f2[1][v] - f2[5][v], d37 = f2[3][v] - f2[7][v];
+        const T d26 = f2[2][v] - f2[6][v], d84 = f2[8][v] - f2[4][v];
+        const T jx = (d15 + d26) + d84;
+        const T jy = (d37 + d26) - d84;
         const T inv_h = recip(h);
         const T ux = jx * inv_h, uy = jy * inv_h;
 
@@ -272,37 +274,29 @@ template <int P, bool KF> struct Stage {
         //   rest: dh - 5 q/6 - 2 h u^2/3
         //   axes: q/6 + h ((c.u)/3 + (c.u)^2/2 - u^2/6)
         //   diagonals: q/24 + h ((c.u)/12 + (c.u)^2/8 - u^2/24)
-        // BGK with forcing: d + omega (deq - d) + 3 w_l c_l.F
+        // BGK with forcing: d + omega (deq - d) + 3 w_l c_l.F.  Opposite
+        // populations l, -l share the even part in c and differ in the sign of
+        // the odd part: post = (1 - omega) d + E +- O with
+        //   E = omega h ((c.u)^2 w2 - u^2 w0) + omega q w0,
+        //   O = w1 (omega h c.u + c.F),  (w0, w1, w2) = (1/6, 1/3, 1/2) on the
+        //   axes and (1/24, 1/12, 1/8) on the diagonals.
         const T usq = madd(ux, ux, uy * uy);
-        const T a1 = usq * T(-1.0 / 6.0);
-        const T a2 = usq * T(-1.0 / 24.0);
         const T hom = h * C.omega;
         const T G = C.omega * (C.g * dh * (h + C.href));  // omega q
-#pragma unroll
-        for (int l = 0; l < 9; ++l) {
-          T poly, src;
-          if (l == 0) {
-            poly = usq * T(-2.0 / 3.0);
-            src = madd(G, T(-5.0 / 6.0), C.omega * dh);
-          } else {
-            const int cx = kCx[l], cy = kCy[l];
-            const T cu = cx == 0 ? (cy > 0 ? uy : -uy)
-                                 : (cy == 0 ? (cx > 0 ? ux : -ux)
-                                            : (cx > 0 ? (cy > 0 ? ux + uy : ux - uy) : (cy > 0 ? uy - ux : -ux - uy)));
-            const T cF = cx == 0 ? (cy > 0 ? Fy : -Fy)
-                                 : (cy == 0 ? (cx > 0 ? Fx : -Fx)
-                                            : (cx > 0 ? (cy > 0 ? Fx + Fy : Fx - Fy) : (cy > 0 ? Fy - Fx : -Fx - Fy)));
-            if (l & 1) {
-              poly = madd(cu, madd(cu, T(0.5), T(1.0 / 3.0)), a1);
-              src = madd(G, T(1.0 / 6.0), cF * T(1.0 / 3.0));
-            } else {
-              poly = madd(cu, madd(cu, T(0.125), T(1.0 / 12.0)), a2);
-              src = madd(G, T(1.0 / 24.0), cF * T(1.0 / 12.0));
-            }
-          }
-          // d + omega (h poly + q-term - d) + forcing = (1 - omega) d + (h omega) poly + src
-          post[l][v] = madd(C.om1, f2[l][v], madd(hom, poly, src));
-        }
+        post[0][v] = madd(C.om1, f2[0][v], madd(hom, usq * T(-2.0 / 3.0), madd(G, T(-5.0 / 6.0), C.omega * dh)));
+        const T evA = madd(hom, usq * T(-1.0 / 6.0), G * T(1.0 / 6.0));    // E without (c.u)^2, axes
+        const T evD = madd(hom, usq * T(-1.0 / 24.0), G * T(1.0 / 24.0));  // and diagonals
+        auto opposite = [&](int lp, int lm, T cu, T cF, T ev, T w1, T w2) {
+          const T hc = hom * cu;
+          const T E = madd(hc, cu * w2, ev);
+          const T O = hc + cF;
+          post[lp][v] = madd(O, w1, madd(C.om1, f2[lp][v], E));
+          post[lm][v] = madd(-O, w1, madd(C.om1, f2[lm][v], E));
+        };
+        opposite(1, 5, ux, Fx, evA, T(1.0 / 3.0), T(0.5));
+        opposite(3, 7, uy, Fy, evA, T(1.0 / 3.0), T(0.5));
+        opposite(2, 6, ux + uy, Fx + Fy, evD, T(1.0 / 12.0), T(0.125));
+        opposite(4, 8, uy - ux, Fy - Fx, evD, T(1.0 / 12.0), T(0.125));
         hv[v] = dh;
         jxv[v] = jx;
         jyv[v] = jy;
@@ -313,8 +307,13 @@ template <int P, bool KF> struct Stage {
     for (int v = 0; v < V + 2; ++v) {
       h2[v] = h1[v];
       h1[v] = h0[v];
-      p3[v] = p2[v];
-      p2[v] = p1[v];
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      dx3[v] = dx2[v];
+      dx2[v] = dx1[v];
+      sm3[v] = sm2[v];
+      sm2[v] = sm1[v];
     }
     return emit;
   }
