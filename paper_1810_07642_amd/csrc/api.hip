@@ -137,6 +137,9 @@ int tflbm_check_params(const tflbm_params *p) {
   const int64_t ldx = ((int64_t)p->nx + 63) / 64 * 64;
   if ((int64_t)p->ny * ldx >= ((int64_t)1 << 31)) return TFLBM_EINVAL;
   if (p->prec < TFLBM_FP64 || p->prec > TFLBM_FP16S) return TFLBM_EINVAL;
+  // one row of records is addressed through a 32-bit buffer range
+  const int64_t nblk = ((int64_t)p->nx + record_sites(p->prec) - 1) / record_sites(p->prec);
+  if (nblk * record_bytes(p->prec) >= ((int64_t)1 << 31)) return TFLBM_EINVAL;
   if (p->n_exp < 1 || p->n_exp > 32 || p->m_exp < 1 || p->m_exp > 32 || p->n_exp == p->m_exp) return TFLBM_EINVAL;
   if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24) return TFLBM_EINVAL;
   if (!is_fin(p->tau) || !(p->tau > 0.5)) return TFLBM_EINVAL;

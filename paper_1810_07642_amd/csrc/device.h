@@ -20,26 +20,33 @@ constexpr double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0, 1.0 / 9.0, 1.0 / 36.
 constexpr double kCs2 = 1.0 / 3.0;
 
 // Storage form of the populations.
-//  V  : consecutive columns owned by one lane of a marching wavefront.
-//  T  : arithmetic type of the step.
-//  B  : sites per record (one marching strip writes exactly one record per
-//       row); a population segment of a record is B elements long and a whole
-//       number of 128-byte lines, so every store covers complete lines.
-//  RB : bytes per record.
+//  V   : consecutive columns owned by one lane of a marching wavefront.
+//  T   : arithmetic type of the step.
+//  B   : sites per record (one marching strip writes exactly one record per
+//        row).  A wavefront covers 64 V columns: B output columns and
+//        (64 V - B)/2 halo columns per side, 6 being what two fused steps
+//        consume (the stencil reaches 3 columns per step).
+//  RB  : bytes per record.
+//  PAD : bytes of padding after each c_ly group of segments, so that every
+//        group fills whole 128-byte lines; the step writes the padding too,
+//        so every line of a full record is written whole.
 template <int P> struct Form;
 template <> struct Form<kF64> {
+  // segments of 416 B; groups of three padded from 1248 to 1280 B (10 lines)
   using T = double;
-  static constexpr int V = 1, B = 48, RB = 9 * 48 * 8;
+  static constexpr int V = 1, B = 52, SEG = 52 * 8, GRP = 1280, RB = 3 * GRP, PAD = GRP - 3 * SEG;
 };
 template <> struct Form<kF32> {
+  // segments of 464 B; groups of three padded from 1392 to 1408 B (11 lines);
+  // 33 lines per record, an odd stride over the HBM channels
   using T = float;
-  static constexpr int V = 2, B = 96, RB = 9 * 96 * 4;
+  static constexpr int V = 2, B = 116, SEG = 116 * 4, GRP = 1408, RB = 3 * GRP, PAD = GRP - 3 * SEG;
 };
 template <> struct Form<kF16S> {
   // 2048 bytes of data padded to 17 lines: a power-of-two record stride puts
   // the same segment of every record on the same few HBM channels
   using T = float;
-  static constexpr int V = 2, B = 96, RB = 2176;
+  static constexpr int V = 2, B = 96, SEG = 0, GRP = 0, RB = 2176, PAD = 64;
 };
 
 // Population layout ("pull in x, push in y").  Records of B consecutive
@@ -54,15 +61,22 @@ constexpr int kSlot[9] = {0, 1, 3, 4, 5, 2, 6, 7, 8};
 
 // Byte offset of the segment of population l inside a record.
 template <int P> __host__ __device__ constexpr int seg_offset(int l) {
-  if constexpr (P == kF64) return kSlot[l] * 48 * 8;
-  else if constexpr (P == kF32) return kSlot[l] * 96 * 4;
-  else {
+  if constexpr (P == kF64 || P == kF32) {
+    return (kSlot[l] / 3) * Form<P>::GRP + (kSlot[l] % 3) * Form<P>::SEG;
+  } else {
     // FP16S: rest population FP32 (384 B), then FP16 segments of 192 B:
     // slots 1-2 at 384, slots 3-5 at 768, slots 6-8 at 1408 (each c_ly group
     // starts on a 128-byte line; the 64 B after slots 3-5 and 6-8 are padding)
     const int s = kSlot[l];
     return s == 0 ? 0 : (s <= 2 ? 384 + (s - 1) * 192 : (s <= 5 ? 768 + (s - 3) * 192 : 1408 + (s - 6) * 192));
   }
+}
+
+// Byte offset of the padding after c_ly group g (0: c_ly = 0, 1: +1, 2: -1),
+// or -1 if the group has none.
+template <int P> __host__ __device__ constexpr int pad_offset(int g) {
+  if constexpr (P == kF64 || P == kF32) return g * Form<P>::GRP + 3 * Form<P>::SEG;
+  else return g == 0 ? -1 : (g == 1 ? 1344 : 1984);
 }
 
 // Everything a step kernel needs, passed by value.

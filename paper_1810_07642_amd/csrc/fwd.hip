@@ -376,16 +376,6 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
           if (L.out[v]) st_f32(rowD[1], L.oe[v], rest[v]);
       }
     }
-    // fill the 64-byte pads after the c_ly = +1 and -1 groups of a full
-    // record so that its lines are written whole
-    if (xend - x0 == B) {
-      const int q16 = lane - HX / V;
-      if (q16 >= 0 && q16 < 16) {
-        const int rec = (x0 / B) * RB;
-        st_f32(rowD[2], rec + 1344 + 4 * q16, 0.f);
-        st_f32(rowD[0], rec + 1984 + 4 * q16, 0.f);
-      }
-    }
   } else if (L.fast_store) {
     // every lane stores all of its columns or none: one masked region
     if (pair) {
@@ -412,6 +402,17 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
             if (L.out[v]) st_f32(rd, L.oe[v] + seg, post[l][v]);
         }
       }
+    }
+  }
+  // zero the padding after each c_ly group of a full record so that its
+  // lines are written whole
+  if (xend - x0 == B) {
+    constexpr int W = Form<P>::PAD / 4;
+    if (lane < W) {
+      const int rec = (x0 / B) * RB;
+#pragma unroll
+      for (int g = 0; g < 3; ++g)
+        if (pad_offset<P>(g) >= 0) st_f32(rowD[g == 0 ? 1 : (g == 1 ? 2 : 0)], rec + pad_offset<P>(g) + 4 * lane, 0.f);
     }
   }
 }
@@ -742,7 +743,7 @@ int step_blocks_per_cu(int prec, bool kf, int ns) {
   }
 }
 
-int record_sites(int prec) { return prec == kF64 ? Form<kF64>::B : Form<kF32>::B; }
+int record_sites(int prec) { return prec == kF64 ? Form<kF64>::B : (prec == kF32 ? Form<kF32>::B : Form<kF16S>::B); }
 int record_bytes(int prec) {
   return prec == kF64 ? Form<kF64>::RB : (prec == kF32 ? Form<kF32>::RB : Form<kF16S>::RB);
 }
