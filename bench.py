@@ -204,7 +204,12 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic[0] / (traffic[1] * ms_step * 1e-3) / 1e9, 1),
                      "kernel": "step_kernel<fp32, kappa field, 2 fused steps>", "site_updates_per_launch": 2,
-                     "bytes_per_site_update": BYTES_PER_SITE["fp32"]},
+                     "bytes_per_site_update": BYTES_PER_SITE["fp32"],
+                     # one launch advances two steps but reads and writes every record once:
+                     # frac above counts the bytes of two separate steps, per_pass the bytes of one pass
+                     "per_pass": {"bytes_per_site": BYTES_PER_SITE["fp32"],
+                                  "achieved": round(achieved / 2, 1),
+                                  "frac": round(achieved / 2 / HBM_PEAK_GBS, 4)}},
     }
     log(f"fp32: {ms_step * 1e3:.1f} us/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic")
 

@@ -35,6 +35,12 @@ int choose_rows(int ny, int nstrips, int slots, int min_rows, const char *env_na
   return rows;
 }
 
+// Shortest row chunk a tile marches.  On small lattices, where one round of
+// tiles cannot fill the GPU anyway, a tile's time is its chain of rows (chunk
+// plus halo rows) and short chunks win; below 4 rows the re-read halo rows
+// (4 for one step, 10 for two fused steps) dominate the traffic.
+constexpr int kMinRows = 4;
+
 // Launch shapes of the step kernels for the device current at the call.
 void plan_launches(tflbm_sim *s) {
   int dev = 0, cus = 256;
@@ -47,13 +53,13 @@ void plan_launches(tflbm_sim *s) {
   int occ2 = step_blocks_per_cu(s->p.prec, s->kfield, 2);
   if (occ1 <= 0) occ1 = 8;
   if (occ2 <= 0) occ2 = 8;
-  s->rows = choose_rows(ny, s->nstrips, occ1 * cus, 8, "TFLBM_ROWS");
+  s->rows = choose_rows(ny, s->nstrips, occ1 * cus, kMinRows, "TFLBM_ROWS");
   s->ntiles = s->nstrips * ((ny + s->rows - 1) / s->rows);
   s->per_xcd = (s->ntiles + 7) / 8;
-  s->rows2 = choose_rows(ny, s->nstrips, occ2 * cus, 16, "TFLBM_ROWS2");
+  s->rows2 = choose_rows(ny, s->nstrips, occ2 * cus, kMinRows, "TFLBM_ROWS2");
   s->ntiles2 = s->nstrips * ((ny + s->rows2 - 1) / s->rows2);
   s->per_xcd2 = (s->ntiles2 + 7) / 8;
-  s->adj_rows = choose_rows(ny, s->adj_nstrips, 2 * cus * 4, 8, "TFLBM_ADJ_ROWS");
+  s->adj_rows = choose_rows(ny, s->adj_nstrips, 2 * cus * 4, kMinRows, "TFLBM_ADJ_ROWS");
   s->adj_ntiles = s->adj_nstrips * ((ny + s->adj_rows - 1) / s->adj_rows);
   s->adj_per_xcd = (s->adj_ntiles + 7) / 8;
 }
