@@ -27,26 +27,28 @@ constexpr double kCs2 = 1.0 / 3.0;
 //        (64 V - B)/2 halo columns per side, 6 being what two fused steps
 //        consume (the stencil reaches 3 columns per step).
 //  RB  : bytes per record.
-//  PAD : bytes of padding after each c_ly group of segments, so that every
-//        group fills whole 128-byte lines; the step writes the padding too,
-//        so every line of a full record is written whole.
+//  Each c_ly group of segments is padded to whole 128-byte lines and the
+//  step writes the padding too, so every line of a full record is written
+//  whole (pad_offset, pad_bytes).
 template <int P> struct Form;
 template <> struct Form<kF64> {
   // segments of 416 B; groups of three padded from 1248 to 1280 B (10 lines)
   using T = double;
-  static constexpr int V = 1, B = 52, SEG = 52 * 8, GRP = 1280, RB = 3 * GRP, PAD = GRP - 3 * SEG;
+  static constexpr int V = 1, B = 52, SEG = 52 * 8, GRP = 1280, RB = 3 * GRP;
 };
 template <> struct Form<kF32> {
   // segments of 464 B; groups of three padded from 1392 to 1408 B (11 lines);
   // 33 lines per record, an odd stride over the HBM channels
   using T = float;
-  static constexpr int V = 2, B = 116, SEG = 116 * 4, GRP = 1408, RB = 3 * GRP, PAD = GRP - 3 * SEG;
+  static constexpr int V = 2, B = 116, SEG = 116 * 4, GRP = 1408, RB = 3 * GRP;
 };
 template <> struct Form<kF16S> {
-  // 2048 bytes of data padded to 17 lines: a power-of-two record stride puts
-  // the same segment of every record on the same few HBM channels
+  // rest deviation FP32 (464 B), 8 FP16 segments of 232 B; groups padded to
+  // 1024, 768 and 768 B, plus one unused line: 21 lines, an odd stride (a
+  // power-of-two record stride puts the same segment of every record on the
+  // same few HBM channels)
   using T = float;
-  static constexpr int V = 2, B = 96, SEG = 0, GRP = 0, RB = 2176, PAD = 64;
+  static constexpr int V = 2, B = 116, SEG = 116 * 2, RB = 2688;
 };
 
 // Population layout ("pull in x, push in y").  Records of B consecutive
@@ -64,19 +66,23 @@ template <int P> __host__ __device__ constexpr int seg_offset(int l) {
   if constexpr (P == kF64 || P == kF32) {
     return (kSlot[l] / 3) * Form<P>::GRP + (kSlot[l] % 3) * Form<P>::SEG;
   } else {
-    // FP16S: rest population FP32 (384 B), then FP16 segments of 192 B:
-    // slots 1-2 at 384, slots 3-5 at 768, slots 6-8 at 1408 (each c_ly group
-    // starts on a 128-byte line; the 64 B after slots 3-5 and 6-8 are padding)
+    // FP16S: rest deviation FP32 at 0, FP16 slots 1-2 at 464, slots 3-5 at
+    // 1024, slots 6-8 at 1792 (each c_ly group starts on a 128-byte line)
+    constexpr int S = Form<kF16S>::SEG;
     const int s = kSlot[l];
-    return s == 0 ? 0 : (s <= 2 ? 384 + (s - 1) * 192 : (s <= 5 ? 768 + (s - 3) * 192 : 1408 + (s - 6) * 192));
+    return s == 0 ? 0 : (s <= 2 ? 2 * S + (s - 1) * S : (s <= 5 ? 1024 + (s - 3) * S : 1792 + (s - 6) * S));
   }
 }
 
-// Byte offset of the padding after c_ly group g (0: c_ly = 0, 1: +1, 2: -1),
-// or -1 if the group has none.
+// Byte offset and size of the padding after c_ly group g (0: c_ly = 0,
+// 1: +1, 2: -1).
 template <int P> __host__ __device__ constexpr int pad_offset(int g) {
   if constexpr (P == kF64 || P == kF32) return g * Form<P>::GRP + 3 * Form<P>::SEG;
-  else return g == 0 ? -1 : (g == 1 ? 1344 : 1984);
+  else return g == 0 ? 4 * Form<kF16S>::SEG : (g == 1 ? 1024 : 1792) + 3 * Form<kF16S>::SEG;
+}
+template <int P> __host__ __device__ constexpr int pad_bytes(int g) {
+  if constexpr (P == kF64 || P == kF32) return Form<P>::GRP - 3 * Form<P>::SEG;
+  else return g == 0 ? 1024 - 4 * Form<kF16S>::SEG : 768 - 3 * Form<kF16S>::SEG;
 }
 
 // Everything a step kernel needs, passed by value.

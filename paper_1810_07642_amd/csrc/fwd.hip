@@ -407,13 +407,10 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
   // zero the padding after each c_ly group of a full record so that its
   // lines are written whole
   if (xend - x0 == B) {
-    constexpr int W = Form<P>::PAD / 4;
-    if (lane < W) {
-      const int rec = (x0 / B) * RB;
+    const int rec = (x0 / B) * RB;
 #pragma unroll
-      for (int g = 0; g < 3; ++g)
-        if (pad_offset<P>(g) >= 0) st_f32(rowD[g == 0 ? 1 : (g == 1 ? 2 : 0)], rec + pad_offset<P>(g) + 4 * lane, 0.f);
-    }
+    for (int g = 0; g < 3; ++g)
+      if (4 * lane < pad_bytes<P>(g)) st_f32(rowD[g == 0 ? 1 : (g == 1 ? 2 : 0)], rec + pad_offset<P>(g) + 4 * lane, 0.f);
   }
 }
 
