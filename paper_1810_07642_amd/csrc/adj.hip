@@ -47,6 +47,27 @@ struct AdjArgs {
 constexpr int kAdjOutW = 60;  // 64 lanes, one column each, two halo columns per side
 int adj_columns_per_strip() { return kAdjOutW; }
 
+// Lambda_F = 3 sum_l w_l c_l mu_l through differences of opposite populations.
+template <typename T>
+__device__ __forceinline__ void lambda_force(const T (&mu)[9], T cA, T cD, T &LFx, T &LFy) {
+  const T d15 = mu[1] - mu[5], d37 = mu[3] - mu[7], d26 = mu[2] - mu[6], d48 = mu[4] - mu[8];
+  LFx = madd(cA, d15, cD * (d26 - d48));
+  LFy = madd(cA, d37, cD * (d26 + d48));
+}
+
+// r^n and r^m; (9, 3) and (3, 9) without loops.
+template <typename T> __device__ __forceinline__ void powers(T r, int n, int m, T &rn, T &rm) {
+  if ((n == 9 && m == 3) || (n == 3 && m == 9)) {
+    const T r3 = r * r * r;
+    const T r9 = r3 * r3 * r3;
+    rn = n == 9 ? r9 : r3;
+    rm = n == 9 ? r3 : r9;
+  } else {
+    rn = ipow(r, n);
+    rm = ipow(r, m);
+  }
+}
+
 template <typename T, bool KF>
 __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
   const int b = blockIdx.x;
@@ -78,6 +99,7 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
   T hC0, hC1, hC2, hL0, hL1, hL2, hR0, hR1, hR2;        // h with left/right neighbours
   T jx0 = 0, jx1 = 0, jx2 = 0, jy0 = 0, jy1 = 0, jy2 = 0;
   T hn, jxn, jyn, kn = 0, k0 = 0, k1 = 0, k2 = 0;
+  T LFx0 = 0, LFy0 = 0, LFx1 = 0, LFy1 = 0, LFx2 = 0, LFy2 = 0;  // Lambda_F of rows r, r-1, r-2
   T gxC0, gxL0, gxR0, gyC0, gyL0, gyR0;                  // lambda_G of rows r, r-1, r-2
   T gxC1, gxL1, gxR1, gyC1, gyL1, gyR1;
   T gxC2, gxL2, gxR2, gyC2, gyL2, gyR2;
@@ -115,6 +137,8 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
     hC2 = hC1; hL2 = hL1; hR2 = hR1;
     hC1 = hC0; hL1 = hL0; hR1 = hR0;
     hC0 = hn;
+    LFx2 = LFx1; LFy2 = LFy1;
+    LFx1 = LFx0; LFy1 = LFy0;
     gxC2 = gxC1; gxL2 = gxL1; gxR2 = gxR1; gyC2 = gyC1; gyL2 = gyL1; gyR2 = gyR1;
     gxC1 = gxC0; gxL1 = gxL0; gxR1 = gxR0; gyC1 = gyC0; gyL1 = gyL0; gyR1 = gyR0;
     const int rn = (ry + 1 == ny) ? 0 : ry + 1;
@@ -124,20 +148,9 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
     hR0 = from_right(hC0);
     {
       // Lambda_F and lambda_G of row r
-      T LFx = cA * mu0[1];
-      LFx += cD * mu0[2];
-      LFx -= cD * mu0[4];
-      LFx -= cA * mu0[5];
-      LFx -= cD * mu0[6];
-      LFx += cD * mu0[8];
-      T LFy = cD * mu0[2];
-      LFy += cA * mu0[3];
-      LFy += cD * mu0[4];
-      LFy -= cD * mu0[6];
-      LFy -= cA * mu0[7];
-      LFy -= cD * mu0[8];
-      gxC0 = -hC0 * LFx;
-      gyC0 = -hC0 * LFy;
+      lambda_force(mu0, cA, cD, LFx0, LFy0);
+      gxC0 = -hC0 * LFx0;
+      gyC0 = -hC0 * LFy0;
       gxL0 = from_left(gxC0);
       gxR0 = from_right(gxC0);
       gyL0 = from_left(gyC0);
@@ -154,9 +167,9 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
       const T odd = ((hR1 + hC0) + hL1) + hC2;
       const T even = ((hR0 + hL0) + hL2) + hR2;
       const T lap = (T(4) * odd + even - T(20) * hC1) * T(1.0 / 6.0);
-      const T rr = hstar / hC1;
-      const T phi = ipow(rr, n_exp) - ipow(rr, m_exp);
-      pC1 = -gamma * (lap + k1 * phi);
+      T rn1, rm1;
+      powers(hstar * recip(hC1), n_exp, m_exp, rn1, rm1);
+      pC1 = -gamma * (lap + k1 * (rn1 - rm1));
       pL1 = from_left(pC1);
       pR1 = from_right(pC1);
       // lambda_p of row r-1 = -div_s lambda_G (lambda_G rows r-2 .. r)
@@ -181,74 +194,63 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
       // output row y = r-2: site quantities from row index 2
       const int y = y0 + (k - 4);
       const T h = hC2;
-      const T inv_h = T(1) / h;
+      const T inv_h = recip(h);
       const T ux = jx2 * inv_h, uy = jy2 * inv_h;
       // forward pressure gradient at y (p rows r-3 .. r-1)
-      T Gx = cA * pR2;
-      Gx += cD * pR1;
-      Gx -= cD * pL1;
-      Gx -= cA * pL2;
-      Gx -= cD * pL3;
-      Gx += cD * pR3;
-      T Gy = cD * pR1;
-      Gy += cA * pC1;
-      Gy += cD * pL1;
-      Gy -= cD * pL3;
-      Gy -= cA * pC3;
-      Gy -= cD * pR3;
+      const T Gx = madd(cA, pR2 - pL2, cD * ((pR1 - pL1) + (pR3 - pL3)));
+      const T Gy = madd(cA, pC1 - pC3, cD * ((pR1 - pR3) + (pL1 - pL3)));
       // Laplacian of lambda_p at y (lambda_p rows r-3 .. r-1)
       const T qodd = ((qR2 + qC1) + qL2) + qC3;
       const T qeven = ((qR1 + qL1) + qL3) + qR3;
       const T lapq = (T(4) * qodd + qeven - T(20) * qC2) * T(1.0 / 6.0);
       const T lp = qC2;
 
-      const T D = T(2) * h * h + T(6) * delta * h + T(3) * delta * delta;
-      const T alpha = T(6) * h / D;
-      const T dalpha = T(6) * (T(3) * delta * delta - T(2) * h * h) / (D * D);
-      const T rr = hstar * inv_h;
-      const T rn_ = ipow(rr, n_exp), rm_ = ipow(rr, m_exp);
+      const T three_d2 = T(3) * delta * delta;
+      const T invD = recip(madd(T(2) * h, h, madd(T(6) * delta, h, three_d2)));
+      const T alpha = T(6) * h * invD;
+      const T dalpha = T(6) * madd(T(-2) * h, h, three_d2) * (invD * invD);
+      T rn_, rm_;
+      powers(hstar * inv_h, n_exp, m_exp, rn_, rm_);
       const T phi = rn_ - rm_;
       const T dphi = (T(m_exp) * rm_ - T(n_exp) * rn_) * inv_h;
+      const T LFx = LFx2, LFy = LFy2;
 
-      T LFx = cA * mu2[1];
-      LFx += cD * mu2[2];
-      LFx -= cD * mu2[4];
-      LFx -= cA * mu2[5];
-      LFx -= cD * mu2[6];
-      LFx += cD * mu2[8];
-      T LFy = cD * mu2[2];
-      LFy += cA * mu2[3];
-      LFy += cD * mu2[4];
-      LFy -= cD * mu2[6];
-      LFy -= cA * mu2[7];
-      LFy -= cD * mu2[8];
-
-      // omega sum_l mu_l dfeq_l/dh and omega sum_l mu_l dfeq_l/du
-      const T usq = ux * ux + uy * uy;
-      T sh = mu2[0] * (T(1) - g * h * T(5.0 / 3.0) - usq * T(2.0 / 3.0));
-      T sux = mu2[0] * (-h * ux * T(4.0 / 3.0));
-      T suy = mu2[0] * (-h * uy * T(4.0 / 3.0));
-#pragma unroll
-      for (int l = 1; l < 9; ++l) {
-        const T cx = T(kCx[l]), cy = T(kCy[l]);
-        const T cu = cx * ux + cy * uy;
-        T dh, c1, c2, c3;
-        if (l & 1) {
-          dh = g * h * T(1.0 / 3.0) + cu * T(1.0 / 3.0) + cu * cu * T(0.5) - usq * T(1.0 / 6.0);
-          c1 = T(1.0 / 3.0); c2 = T(1.0); c3 = T(1.0 / 3.0);
-        } else {
-          dh = g * h * T(1.0 / 12.0) + cu * T(1.0 / 12.0) + cu * cu * T(0.125) - usq * T(1.0 / 24.0);
-          c1 = T(1.0 / 12.0); c2 = T(0.25); c3 = T(1.0 / 12.0);
-        }
-        // dfeq/du = h (c1 c + c2 (c.u) c - c3 u)
-        sh += mu2[l] * dh;
-        const T m = mu2[l] * h;
-        sux += m * (c1 * cx + c2 * cu * cx - c3 * ux);
-        suy += m * (c1 * cy + c2 * cu * cy - c3 * uy);
-      }
+      // omega sum_l mu_l dfeq_l/dh and omega sum_l mu_l dfeq_l/du over pairs
+      // of opposite populations: S = mu_l + mu_-l takes the parts of the
+      // derivatives even in c, D = mu_l - mu_-l the odd ones
+      const T usq = madd(ux, ux, uy * uy);
+      const T gh = g * h;
+      const T up = ux + uy, um = uy - ux;
+      const T S15 = mu2[1] + mu2[5], D15 = mu2[1] - mu2[5];
+      const T S37 = mu2[3] + mu2[7], D37 = mu2[3] - mu2[7];
+      const T S26 = mu2[2] + mu2[6], D26 = mu2[2] - mu2[6];
+      const T S48 = mu2[4] + mu2[8], D48 = mu2[4] - mu2[8];
+      // d/dh: rest 1 - 5gh/3 - 2u^2/3; axes gh/3 + cu/3 + cu^2/2 - u^2/6;
+      // diagonals gh/12 + cu/12 + cu^2/8 - u^2/24
+      T sh = mu2[0] * madd(gh, T(-5.0 / 3.0), madd(usq, T(-2.0 / 3.0), T(1)));
+      sh = madd(S15 + S37, madd(gh, T(1.0 / 3.0), usq * T(-1.0 / 6.0)), sh);
+      sh = madd(T(0.5), madd(S15, ux * ux, S37 * (uy * uy)), sh);
+      sh = madd(T(1.0 / 3.0), madd(D15, ux, D37 * uy), sh);
+      sh = madd(S26 + S48, madd(gh, T(1.0 / 12.0), usq * T(-1.0 / 24.0)), sh);
+      sh = madd(T(0.125), madd(S26, up * up, S48 * (um * um)), sh);
+      sh = madd(T(1.0 / 12.0), madd(D26, up, D48 * um), sh);
+      // d/du = h (c1 c + c2 (c.u) c - c3 u): rest -4u/3; axes (1/3, 1, 1/3);
+      // diagonals (1/12, 1/4, 1/12)
+      T sx = mu2[0] * ux * T(-4.0 / 3.0);
+      sx = madd(D15, T(1.0 / 3.0), sx);
+      sx = madd(S15 - T(0.5) * S37, ux * T(2.0 / 3.0), sx);
+      sx = madd(D26 - D48, T(1.0 / 12.0), sx);
+      sx = madd(S26, madd(up, T(0.25), ux * T(-1.0 / 12.0)), sx);
+      sx = madd(S48, madd(um, T(-0.25), ux * T(-1.0 / 12.0)), sx);
+      T sy = mu2[0] * uy * T(-4.0 / 3.0);
+      sy = madd(D37, T(1.0 / 3.0), sy);
+      sy = madd(S37 - T(0.5) * S15, uy * T(2.0 / 3.0), sy);
+      sy = madd(D26 + D48, T(1.0 / 12.0), sy);
+      sy = madd(S26, madd(up, T(0.25), uy * T(-1.0 / 12.0)), sy);
+      sy = madd(S48, madd(um, T(0.25), uy * T(-1.0 / 12.0)), sy);
       const T fric = nu * alpha;
-      T lux = omega * sux - fric * LFx;
-      T luy = omega * suy - fric * LFy;
+      const T lux = madd(omega * h, sx, -fric * LFx);
+      const T luy = madd(omega * h, sy, -fric * LFy);
       T lh = omega * sh + LFx * (-Gx - nu * dalpha * ux + ax) + LFy * (-Gy - nu * dalpha * uy + ay) -
              gamma * lapq - gamma * k2 * dphi * lp;
       lh -= (lux * ux + luy * uy) * inv_h;
@@ -257,10 +259,14 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
       const int yN = (y + 1 == ny) ? 0 : y + 1;
       const int yS = (y == 0) ? ny - 1 : y - 1;
       T *dst = (T *)A.dst;
+      const T om1 = T(1) - omega;
 #pragma unroll
       for (int l = 0; l < 9; ++l) {
         const int cx = kCx[l], cy = kCy[l];
-        const T lam = (T(1) - omega) * mu2[l] + lh + T(cx) * ljx + T(cy) * ljy;
+        const T cl = cx == 0 ? (cy == 0 ? T(0) : (cy > 0 ? ljy : -ljy))
+                             : (cy == 0 ? (cx > 0 ? ljx : -ljx)
+                                        : (cx > 0 ? (cy > 0 ? ljx + ljy : ljx - ljy) : (cy > 0 ? ljy - ljx : -ljx - ljy)));
+        const T lam = madd(om1, mu2[l], lh + cl);
         // store at x - c_l
         const int yd = cy == 0 ? y : (cy > 0 ? yS : yN);
         const int xd = cx == 0 ? col : (cx > 0 ? colW : colE);

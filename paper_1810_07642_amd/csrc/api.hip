@@ -231,11 +231,13 @@ static int run_steps(tflbm_sim *sim, int64_t nsteps, void *d_capture, tflbm_stre
   hipStream_t st = (hipStream_t)stream;
   const size_t cap_bytes = tflbm_capture_bytes(sim);
   int64_t i = 0;
-  if (!d_capture && sim->fuse == 2) {
-    // two fused steps per pass while at least two remain
+  if (sim->fuse == 2) {
+    // two fused steps per pass while at least two remain (with capture: the
+    // moments of step i and of step i + 1, one capture block apart)
     for (; i + 2 <= nsteps; i += 2) {
       StepArgs A = make_step_args(sim, 2);
-      const int rc = hip_status(sim, launch_step2(sim->p.prec, A, sim->kfield, st));
+      A.capture = d_capture ? (char *)d_capture + (size_t)i * cap_bytes : nullptr;
+      const int rc = hip_status(sim, launch_step2(sim->p.prec, A, sim->kfield, d_capture != nullptr, st));
       if (rc) return rc;
       sim->cur ^= 1;
       sim->steps += 2;

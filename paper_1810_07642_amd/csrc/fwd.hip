@@ -433,11 +433,37 @@ __device__ __forceinline__ void fp16s_roundtrip(float (&post)[9][V], const float
   }
 }
 
+// Moments (h, jx, jy) of row q of the pre-collision state of one step, for
+// the reverse sweep, into the capture planes at `base` ([3][ny][ldx] in T).
+template <int P>
+__device__ __forceinline__ void capture_row(const StepArgs &A, char *base, int q, const typename Form<P>::T (&hv)[Form<P>::V],
+                                            const typename Form<P>::T (&jxv)[Form<P>::V],
+                                            const typename Form<P>::T (&jyv)[Form<P>::V], const Lane<P> &L,
+                                            typename Form<P>::T href) {
+  using T = typename Form<P>::T;
+  constexpr int ES = sizeof(T);
+  const uint32_t prb = (uint32_t)(A.ldx * ES);
+  const size_t ro = (size_t)q * prb;
+  const rsrc_t c0 = make_rsrc(base + ro, prb);
+  const rsrc_t c1 = make_rsrc(base + (size_t)A.plane * ES + ro, prb);
+  const rsrc_t c2 = make_rsrc(base + 2 * (size_t)A.plane * ES + ro, prb);
+#pragma unroll
+  for (int v = 0; v < Form<P>::V; ++v) {
+    if (L.out[v]) {
+      st_t(c0, L.col[v] * ES, href + hv[v]);
+      st_t(c1, L.col[v] * ES, jxv[v]);
+      st_t(c2, L.col[v] * ES, jyv[v]);
+    }
+  }
+}
+
 // NS fused time steps per pass (1 or 2).  Stage 0 consumes the stored rows;
 // with NS = 2 its post-collision rows are streamed in registers into stage 1
 // (rows arrive one row late: row q of the next step needs the post-collision
 // values of rows q-1, q, q+1), whose output is stored.  The strip's chunk
-// reads 2 + 3 (NS - 1) halo rows above and below.
+// reads 2 + 3 (NS - 1) halo rows above and below.  With CAP the moments of
+// each step's pre-collision state on the tile's own rows go to the capture:
+// step t at A.capture, step t + 1 one capture block (3 planes) later.
 template <int P, bool KF, bool CAP, int NS>
 __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   using T = typename Form<P>::T;
@@ -521,25 +547,14 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
       const int q = y0 - HALO + k - 2;  // row of the post-collision values (unwrapped)
       if constexpr (NS == 1) {
         store_row<P>(A, q, post, hv, L, x0, xend, lane);
-        if constexpr (CAP) {
-          const uint32_t prb = (uint32_t)(A.ldx * ES);
-          const size_t ro = (size_t)q * prb;
-          const rsrc_t c0 = make_rsrc(A.capture + ro, prb);
-          const rsrc_t c1 = make_rsrc(A.capture + (size_t)A.plane * ES + ro, prb);
-          const rsrc_t c2 = make_rsrc(A.capture + 2 * (size_t)A.plane * ES + ro, prb);
-#pragma unroll
-          for (int v = 0; v < V; ++v) {
-            if (L.out[v]) {
-              st_t(c0, L.col[v] * ES, C.href + hv[v]);
-              st_t(c1, L.col[v] * ES, jxv[v]);
-              st_t(c2, L.col[v] * ES, jyv[v]);
-            }
-          }
-        }
+        if constexpr (CAP) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href);
       } else {
         // row q - 1 of the next step is complete: c_ly = +1 populations from
         // row q - 2, c_ly = 0 from row q - 1, c_ly = -1 from row q
         const int e = k - 4;  // emission index; q = y0 - 3 + e
+        if constexpr (CAP) {
+          if (q >= y0 && q < yend) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href);
+        }
         if constexpr (P == kF16S) fp16s_roundtrip<V>(post, hv, A);  // as if stored and reloaded
         T g[9][V];
         shift_x<T, V>(6, post[6], g[6]);
@@ -569,7 +584,10 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
           T g2[9][V];
           S1.ingest(j, rowB1, g, g2, L, A, lane);
           T post2[9][V], hv2[V], jx2[V], jy2[V];
-          if (S1.finish(j, g2, post2, hv2, jx2, jy2, C, L, bad)) store_row<P>(A, y0 - 4 + j, post2, hv2, L, x0, xend, lane);
+          if (S1.finish(j, g2, post2, hv2, jx2, jy2, C, L, bad)) {
+            store_row<P>(A, y0 - 4 + j, post2, hv2, L, x0, xend, lane);
+            if constexpr (CAP) capture_row<P>(A, A.capture + 3 * A.plane * ES, y0 - 4 + j, hv2, jx2, jy2, L, C.href);
+          }
         }
       }
     }
@@ -696,8 +714,13 @@ static hipError_t launch_step_p(const StepArgs &A, bool kf, bool cap, hipStream_
       else step_kernel<P, false, false, 1><<<grid, block, 0, s>>>(A);
     }
   } else {
-    if (kf) step_kernel<P, true, false, 2><<<grid, block, 0, s>>>(A);
-    else step_kernel<P, false, false, 2><<<grid, block, 0, s>>>(A);
+    if (kf) {
+      if (cap) step_kernel<P, true, true, 2><<<grid, block, 0, s>>>(A);
+      else step_kernel<P, true, false, 2><<<grid, block, 0, s>>>(A);
+    } else {
+      if (cap) step_kernel<P, false, true, 2><<<grid, block, 0, s>>>(A);
+      else step_kernel<P, false, false, 2><<<grid, block, 0, s>>>(A);
+    }
   }
   return hipGetLastError();
 }
@@ -710,11 +733,11 @@ hipError_t launch_step(int prec, const StepArgs &A, bool kf, bool cap, hipStream
   }
 }
 
-hipError_t launch_step2(int prec, const StepArgs &A, bool kf, hipStream_t s) {
+hipError_t launch_step2(int prec, const StepArgs &A, bool kf, bool cap, hipStream_t s) {
   switch (prec) {
-    case kF64: return launch_step_p<kF64, 2>(A, kf, false, s);
-    case kF32: return launch_step_p<kF32, 2>(A, kf, false, s);
-    default: return launch_step_p<kF16S, 2>(A, kf, false, s);
+    case kF64: return launch_step_p<kF64, 2>(A, kf, cap, s);
+    case kF32: return launch_step_p<kF32, 2>(A, kf, cap, s);
+    default: return launch_step_p<kF16S, 2>(A, kf, cap, s);
   }
 }
 

@@ -16,7 +16,7 @@ hipError_t launch_step(int prec, const StepArgs &A, bool kfield, bool capture, h
 // Resident one-wavefront workgroups per CU of the step kernel (0 if unknown).
 int step_blocks_per_cu(int prec, bool kfield, int ns);
 // Two fused time steps in one pass (src at time t, dst at time t + 2).
-hipError_t launch_step2(int prec, const StepArgs &A, bool kfield, hipStream_t s);
+hipError_t launch_step2(int prec, const StepArgs &A, bool kfield, bool capture, hipStream_t s);
 hipError_t launch_init(int prec, const StepArgs &A, const double *h0, const double *theta, double kconst,
                        hipStream_t s);
 hipError_t launch_read(int prec, const StepArgs &A, double *h, double *ux, double *uy, hipStream_t s);

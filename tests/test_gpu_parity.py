@@ -236,3 +236,28 @@ def test_fused_steps_equal_single_steps_bitwise(prec, href):
             states.append((sim.state_save().cpu(),) + tuple(t.cpu() for t in sim.read()))
         for a, b in zip(states[0], states[1]):
             assert torch.equal(a, b), (prec, href, ny, nx)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_fused_capture_equals_single_step_capture_bitwise(prec):
+    """The capture of the reverse sweep (h, jx, jy of every step) written by
+    the fused two-step pass equals the one written step by step, and the
+    final state too, on ragged grids with an odd step count."""
+    import os
+    from paper_1810_07642_amd import Sim
+    p = dict(tau=0.9, gamma=0.01, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5, ay=-1e-5, href=0.4)
+    for (ny, nx) in [(70, 150), (23, 37), (6, 300)]:
+        h0, th = random_case(ny, nx, 43)
+        out = []
+        for fuse in ("2", "1"):
+            os.environ["TFLBM_FUSE"] = fuse
+            try:
+                sim = Sim(nx, ny, prec, **p).init(h0, th)
+            finally:
+                del os.environ["TFLBM_FUSE"]
+            cap = torch.zeros(7 * sim.capture_bytes(), dtype=torch.uint8, device="cuda")
+            sim.step_capture(7, cap)
+            sim.check()
+            out.append((cap.cpu(), sim.state_save().cpu()))
+        assert torch.equal(out[0][0], out[1][0]), (prec, ny, nx, "capture")
+        assert torch.equal(out[0][1], out[1][1]), (prec, ny, nx, "state")
