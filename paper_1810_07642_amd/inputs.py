@@ -167,6 +167,18 @@ def inverse_design(n=512, seed=3, target_seed=4, hstar=0.09):
     return p, h0, th, target
 
 
+def stripe_recovery(n=128, seed=5, hstar=0.095, period=32):
+    """Twin experiment for the inverse-design loop: flat film h0 = 0.1 +
+    1e-4 U(-1, 1) on h_* = 0.095 (thin enough, h0 < 1.2 h_*, that the film is
+    spinodally stable and its response to theta is smooth), gamma = 0.01,
+    tau = 1, delta = 1, and the true pattern: stripes of period 32 alternating
+    pi/9 and pi/4 with sine ramps of width 4."""
+    p = params(hstar=hstar, delta=1.0)
+    h0 = noisy_film(n, n, 0.1, 1.0e-4, seed)
+    th = stripe_theta(n, n, math.pi / 9, math.pi / 4, period, 4.0)
+    return p, h0, th
+
+
 def random_pixels(ny, nx, count, seed):
     """``count`` distinct seeded (y, x) sites."""
     gen = torch.Generator().manual_seed(int(seed))
