@@ -10,10 +10,11 @@ Modules:
   grad  -- autograd gradient through the forward step, with recompute.
   local -- one-site-at-a-time evaluation on periodic windows, for sampled
            checks at grid sizes the whole-array oracle cannot afford.
+  diag  -- term-balance diagnostic of the appendix (eq. "magnitude").
 
 Parity status: every function is pinned by the CPU tests in
 ``tests/test_oracle_*.py`` (moment identities, stencil closed forms, exact
 recurrences, a hand-derived Fourier propagator, disjoining integral, mass
 invariance, contact angle of a relaxed drop); none is "parity unpinned".
 """
-from . import lbm, grad, local  # noqa: F401
+from . import lbm, grad, local, diag  # noqa: F401
