@@ -157,6 +157,19 @@ int tflbm_mass(const tflbm_sim *sim, double *h_mass, tflbm_stream_t stream);
  * h <= 0 or a non-finite h at an updated site, or if h0 had such a value. */
 int tflbm_check(const tflbm_sim *sim, tflbm_stream_t stream);
 
+/* (blocking) Term-balance diagnostic (appendix, eq. "magnitude"): h_norms[0..7]
+ * (host memory, 8 doubles) receive (N^-1 sum_x phi^2)^(1/2), N = nx ny, of the
+ * x then the y components of the terms of the depth-averaged momentum
+ * equation (eq. "hydro2") at the current pre-collision state:
+ *   [0] -h d_x p_film        [1] -nu alpha_delta(h) u_x
+ *   [2] nu lap(h u_x) + 2 nu d_x(div(h u))   [3] d_x(j_x u_x) + d_y(j_y u_x)
+ *   [4..7] the same for y.
+ * Derivatives are the isotropic stencils of the step (eqs. "derivative",
+ * "n_laplace"); d_x(div j) applies the derivative stencil to the stencil
+ * divergence.  Evaluated in FP64 from the stored populations and reduced in
+ * a fixed order (deterministic).  TFLBM_ESTATE before tflbm_init. */
+int tflbm_term_norms(const tflbm_sim *sim, double *h_norms, tflbm_stream_t stream);
+
 /* Bytes of one population buffer (a checkpoint of the state). */
 size_t tflbm_state_bytes(const tflbm_sim *sim);
 

@@ -179,7 +179,7 @@ int tflbm_create(const tflbm_params *p, tflbm_sim **out) {
   s->off_b = o; o = align_up(o + s->pop_bytes, 4096);
   s->off_k = o; o = align_up(o + s->kf_bytes, 4096);
   s->off_flag = o; o = align_up(o + 256, 256);
-  s->off_part = o; o = align_up(o + 8 * (size_t)s->n_partials, 256);
+  s->off_part = o; o = align_up(o + 8 * 8 * (size_t)s->n_partials, 256);  // up to 8 sums per workgroup
   s->off_out = o; o = align_up(o + 256, 4096);
   s->ws_bytes = o;
   s->kconst = (double)((p->n_exp - 1) * (p->m_exp - 1)) / ((double)(p->n_exp - p->m_exp) * p->hstar);
@@ -282,6 +282,20 @@ int tflbm_mass(const tflbm_sim *sim, double *h_mass, tflbm_stream_t stream) {
                                        (double *)(sim->ws + sim->off_out), st));
   if (rc) return rc;
   rc = hip_status(sim, hipMemcpyAsync(h_mass, sim->ws + sim->off_out, sizeof(double), hipMemcpyDeviceToHost, st));
+  if (rc) return rc;
+  return hip_status(sim, hipStreamSynchronize(st));
+}
+
+int tflbm_term_norms(const tflbm_sim *sim, double *h_norms, tflbm_stream_t stream) {
+  if (!sim || !h_norms) return TFLBM_EINVAL;
+  if (!sim->initialised) return TFLBM_ESTATE;
+  hipStream_t st = (hipStream_t)stream;
+  StepArgs A = make_step_args(sim);
+  const int nb = terms_blocks(sim->p.nx, sim->p.ny, sim->n_partials);
+  int rc = hip_status(sim, launch_terms(sim->p.prec, A, sim->kfield, (double *)(sim->ws + sim->off_part), nb,
+                                        (double *)(sim->ws + sim->off_out), st));
+  if (rc) return rc;
+  rc = hip_status(sim, hipMemcpyAsync(h_norms, sim->ws + sim->off_out, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
   if (rc) return rc;
   return hip_status(sim, hipStreamSynchronize(st));
 }

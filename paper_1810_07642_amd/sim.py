@@ -131,6 +131,16 @@ class Sim:
         """Raises TFLBMError(TFLBM_ENONFINITE) if a step met h <= 0 or non-finite h."""
         self._chk(self.lib.tflbm_check(self.h, self.stream), "tflbm_check")
 
+    TERM_NAMES = ("pressure_x", "friction_x", "viscous_x", "advection_x",
+                  "pressure_y", "friction_y", "viscous_y", "advection_y")
+
+    def term_norms(self):
+        """Term-balance diagnostic of the current state (appendix, eq.
+        "magnitude"): a dict name -> L2 norm over the lattice."""
+        out = (ctypes.c_double * 8)()
+        self._chk(self.lib.tflbm_term_norms(self.h, out, self.stream), "tflbm_term_norms")
+        return dict(zip(self.TERM_NAMES, list(out)))
+
     def status(self):
         return self.lib.tflbm_check(self.h, self.stream)
 
