@@ -6,6 +6,7 @@ include/tflbm.h); this package is its thin Python binding:
   Sim        -- one lattice: init / step / read / mass / check / checkpoints / adjoint
   TFLBMRun   -- torch.autograd.Function: gradient of the final height w.r.t. h0 and theta
   design     -- inverse design: Adam on theta(x, y) through TFLBMRun (fit_contact_angle)
+  spreading  -- spreading-drop tracking: cap geometry, Tanner exponent, Cox-Voinov fit
   inputs     -- seeded synthetic initial conditions and parameter sets
   build      -- compiles libtflbm.so
 """
