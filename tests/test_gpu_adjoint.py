@@ -114,3 +114,56 @@ def test_adjoint_against_finite_differences_fp64():
             checked += 1
             assert abs(fds[1] - float(g[y, x])) <= 1e-5 * scale, (which, y, x, fds, float(g[y, x]))
     assert checked >= 24
+
+
+def test_adjoint_full_inverse_design_config():
+    """The inverse-design configuration at full size: 512 x 512 dewetting recipe,
+    4096 steps, checkpoints every 64, L = 1/2 sum (h_N - target)^2.  The FP64
+    adjoint gradient w.r.t. theta and h0 against central differences of the HIP
+    FP64 forward (eps = 2e-5, cross-checked with eps/2; the film ruptures over
+    4096 steps, so a pixel whose two differences disagree is skipped and at
+    least half of the 64 checks must converge) at 32 seeded pixels; the
+    gradient of the FP32 forward (FP32 adjoint, FP64 kappa-gradient
+    accumulation) against the FP64 one over the whole field."""
+    from paper_1810_07642_amd import Sim, TFLBMRun
+    banner("full inverse-design config 512^2 x 4096, K = 64")
+    n, steps, K = 512, 4096, 64
+    p, h0, th, target = inputs.inverse_design(n=n)
+    tgt = target.cuda()
+    grads = {}
+    for prec in ("fp64", "fp32"):
+        h0c = h0.cuda().requires_grad_(True)
+        thc = th.cuda().requires_grad_(True)
+        h = TFLBMRun.apply(h0c, thc, p, steps, K, prec)
+        (0.5 * ((h - tgt) ** 2).sum()).backward()
+        grads[prec] = (h0c.grad.cpu(), thc.grad.cpu())
+    gh0, gth = grads["fp64"]
+
+    def loss(hh0, tth):
+        sim = Sim(n, n, "fp64", **p).init(hh0, tth)
+        sim.step(steps)
+        sim.check()
+        return float(0.5 * ((sim.height() - tgt) ** 2).sum())
+
+    checked = 0
+    for (y, x) in inputs.random_pixels(n, n, 32, seed=11):
+        for which, g in (("h0", gh0), ("theta", gth)):
+            fds = []
+            for eps in (2e-5, 1e-5):
+                a = h0.clone(); b = th.clone()
+                c = h0.clone(); d = th.clone()
+                if which == "h0":
+                    a[y, x] += eps; c[y, x] -= eps
+                else:
+                    b[y, x] += eps; d[y, x] -= eps
+                fds.append((loss(a, b) - loss(c, d)) / (2 * eps))
+            scale = float(g.abs().max())
+            if abs(fds[0] - fds[1]) > 1e-6 * scale:
+                continue  # FD itself not converged at this pixel
+            checked += 1
+            assert abs(fds[1] - float(g[y, x])) <= 1e-5 * scale, (which, y, x, fds, float(g[y, x]))
+    assert checked >= 32
+    e_h0 = rel_l2(grads["fp32"][0], gh0)
+    e_th = rel_l2(grads["fp32"][1], gth)
+    print(f"FD pixels checked {checked}/64; FP32-forward gradient vs FP64: rel L2 h0 {e_h0:.2e}, theta {e_th:.2e}")
+    assert e_h0 < 1e-2 and e_th < 1e-2
