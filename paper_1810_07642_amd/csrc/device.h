@@ -150,6 +150,11 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Decoded FP16S deviation q * 2^-s.  Written as a fused multiply-add with a
+// zero addend (the same rounded product) so that the conversion and the
+// scaling can issue as one mixed-precision instruction.
+__device__ __forceinline__ float dec16(__half q, float qinv) { return __builtin_fmaf(__half2float(q), qinv, 0.0f); }
+
 // Value of `v` held by lane - 1 (own value on lane 0) / lane + 1 (own value on
 // lane 63): DPP whole-wavefront shifts by one lane (wave_shr:1 = 0x138,
 // wave_shl:1 = 0x130), VALU moves that the compiler can fold into the
@@ -213,7 +218,7 @@ __device__ __forceinline__ typename Form<P>::T pop_at(const char *buf, int l, in
   else if constexpr (P == kF32) return ((const float *)rec)[pos];
   else {
     if (l == 0) return ((const float *)rec)[pos];
-    return __half2float(((const __half *)rec)[pos]) * A.qinv;
+    return dec16(((const __half *)rec)[pos], A.qinv);
   }
 }
 

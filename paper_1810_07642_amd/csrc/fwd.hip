@@ -62,11 +62,11 @@ __device__ __forceinline__ void load_raw(rsrc_t row, int l, const int *oe, const
     } else {
       if (vec) {
         const __half2 q = ld_f16x2(row, o16[0] + seg);
-        out[0] = __low2float(q) * A.qinv;
-        out[1] = __high2float(q) * A.qinv;
+        out[0] = dec16(__low2half(q), A.qinv);
+        out[1] = dec16(__high2half(q), A.qinv);
       } else {
 #pragma unroll
-        for (int v = 0; v < V; ++v) out[v] = __half2float(ld_f16(row, o16[v] + seg)) * A.qinv;
+        for (int v = 0; v < V; ++v) out[v] = dec16(ld_f16(row, o16[v] + seg), A.qinv);
       }
     }
   }
@@ -346,7 +346,7 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         q[l][v] = __float2half_rn(post[l][v] * A.qscale);
-        rest[v] -= __half2float(q[l][v]) * A.qinv;  // rest deviation absorbs the rounding
+        rest[v] -= dec16(q[l][v], A.qinv);  // rest deviation absorbs the rounding
       }
     }
     if (L.fast_store) {
@@ -425,7 +425,7 @@ __device__ __forceinline__ void fp16s_roundtrip(float (&post)[9][V], const float
 #pragma unroll
     for (int l = 1; l < 9; ++l) {
       const __half q = __float2half_rn(post[l][v] * A.qscale);
-      const float d = __half2float(q) * A.qinv;
+      const float d = dec16(q, A.qinv);
       rest -= d;
       post[l][v] = d;
     }
@@ -637,7 +637,7 @@ __global__ void init_kernel(StepArgs A, const double *h0, const double *theta, d
     for (int l = 1; l < 9; ++l) {
       const __half dq = __float2half_rn((float)e[l] * A.qscale);
       *(__half *)pop_ptr<P>(A.dst, l, y, wrap(x - kCx[l], A.nx), A) = dq;
-      sumd += (double)(__half2float(dq) * A.qinv);
+      sumd += (double)dec16(dq, A.qinv);
     }
     *(float *)pop_ptr<P>(A.dst, 0, y, x, A) = (float)(dh - sumd);
   }
