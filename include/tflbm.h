@@ -190,7 +190,9 @@ int tflbm_state_load(tflbm_sim *sim, const void *d_src, int64_t step, tflbm_stre
  * The adjoint state is stored in the working precision (FP64 for
  * TFLBM_FP64, FP32 otherwise); the kappa gradient accumulates in FP64. */
 
-/* Bytes of one step's capture: h, h u_x, h u_y at the start of the step. */
+/* Bytes of one step's capture: h, h u_x, h u_y at the start of the step, in
+ * the working type, laid out in records of the population records' columns
+ * (internal layout, read only by tflbm_adj_step). */
 size_t tflbm_capture_bytes(const tflbm_sim *sim);
 
 /* (async) Like tflbm_step, and also writes the capture of step i

@@ -34,10 +34,11 @@ namespace tflbm {
 struct AdjArgs {
   const char *src;     // mu at the end of step t: [9][ny][ldx] in T
   char *dst;           // mu at the end of step t-1
-  const char *cap;     // h, jx, jy of step t: [3][ny][ldx] in T
+  const char *cap;     // h, jx, jy of step t: capture records of the forward form
   const void *kfield;  // kappa [ny][ldx] in T or nullptr
   double *gk;          // dLoss/dkappa [ny][ldx] FP64
   int nx, ny, ldx;
+  int cnblk;           // capture records per row (those of the forward step)
   int64_t plane;
   int nstrips, H, ntiles, per_xcd;
   int n_exp, m_exp;
@@ -45,6 +46,18 @@ struct AdjArgs {
 };
 
 constexpr int kAdjOutW = 60;  // 64 lanes, one column each, two halo columns per side
+
+// The forward form whose capture records the reverse step reads (FP32 and
+// FP16S share the record geometry).
+template <typename T> struct CapForm;
+template <> struct CapForm<double> {
+  static constexpr int B = Form<kF64>::B, CRB = cap_record_bytes<kF64>();
+};
+template <> struct CapForm<float> {
+  static constexpr int B = Form<kF32>::B, CRB = cap_record_bytes<kF32>();
+  static_assert(Form<kF16S>::B == Form<kF32>::B && cap_record_bytes<kF16S>() == cap_record_bytes<kF32>(),
+                "FP32 and FP16S capture records must agree");
+};
 int adj_columns_per_strip() { return kAdjOutW; }
 
 // Lambda_F = 3 sum_l w_l c_l mu_l through differences of opposite populations.
@@ -92,7 +105,10 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
   const T cA = (T)(3.0 * kW[1]), cD = (T)(3.0 * kW[2]);
   const int n_exp = A.n_exp, m_exp = A.m_exp;
   const T *mu_src = (const T *)A.src;
-  const T *capt = (const T *)A.cap;
+  // byte offset of this lane's column in a row of capture records
+  constexpr int CB = CapForm<T>::B, CRB = CapForm<T>::CRB, CSEG = CB * (int)sizeof(T);
+  const int crec = (col / CB) * CRB + (col % CB) * (int)sizeof(T);
+  const size_t crow = (size_t)A.cnblk * CRB;
 
   // rolling rows: index 0 = row r (newest), 1 = r-1, 2 = r-2
   T mu0[9], mu1[9], mu2[9], mun[9];
@@ -117,9 +133,10 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
     const size_t o = (size_t)row * ldx + col;
 #pragma unroll
     for (int l = 0; l < 9; ++l) mun[l] = mu_src[(size_t)l * plane + o];
-    hn = capt[o];
-    jxn = capt[plane + o];
-    jyn = capt[2 * plane + o];
+    const char *cr = A.cap + (size_t)row * crow + crec;
+    hn = *(const T *)cr;
+    jxn = *(const T *)(cr + CSEG);
+    jyn = *(const T *)(cr + 2 * CSEG);
     if constexpr (KF) kn = ((const T *)A.kfield)[o];
   };
   load_row(ry);
@@ -364,6 +381,7 @@ static AdjArgs make_adj_args(const tflbm_sim *s, void *d_adj) {
   B.nx = s->p.nx;
   B.ny = s->p.ny;
   B.ldx = s->ldx;
+  B.cnblk = s->nblk;
   B.plane = s->plane;
   B.nstrips = s->adj_nstrips;
   B.H = s->adj_rows;

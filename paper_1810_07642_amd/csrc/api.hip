@@ -333,7 +333,7 @@ int tflbm_state_load(tflbm_sim *sim, const void *d_src, int64_t step, tflbm_stre
 }
 
 size_t tflbm_capture_bytes(const tflbm_sim *sim) {
-  return sim ? 3 * (size_t)sim->plane * work_bytes(sim->p.prec) : 0;
+  return sim ? (size_t)sim->p.ny * sim->nblk * capture_record_bytes(sim->p.prec) : 0;
 }
 
 }  // extern "C"

@@ -74,6 +74,14 @@ template <int P> __host__ __device__ constexpr int seg_offset(int l) {
   }
 }
 
+// Capture of one step (the moments h, h u_x, h u_y of the pre-collision state,
+// for the reverse sweep): records of the same B columns, [ny][ceil(nx/B)]
+// [record], each holding the three B-element segments of the working type and
+// padded to whole 128-byte lines, so the step writes whole lines.
+template <int P> __host__ __device__ constexpr int cap_record_bytes() {
+  return (3 * Form<P>::B * (int)sizeof(typename Form<P>::T) + 127) / 128 * 128;
+}
+
 // Byte offset and size of the padding after c_ly group g (0: c_ly = 0,
 // 1: +1, 2: -1).
 template <int P> __host__ __device__ constexpr int pad_offset(int g) {

@@ -77,6 +77,7 @@ template <int P> struct Lane {
   static constexpr int V = Form<P>::V;
   int col[V];         // lattice column of each of the lane's V columns
   int oe[V], o16[V];  // byte offset in a row of records: working-type and FP16 segments
+  int oc[V];          // byte offset in a row of capture records
   bool out[V];        // the column is an output of this strip
   bool vec;           // the column pair lies in one record, 8-byte aligned
   bool vecp;          // the column pair is contiguous and aligned in a plane array
@@ -434,27 +435,41 @@ __device__ __forceinline__ void fp16s_roundtrip(float (&post)[9][V], const float
 }
 
 // Moments (h, jx, jy) of row q of the pre-collision state of one step, for
-// the reverse sweep, into the capture planes at `base` ([3][ny][ldx] in T).
+// the reverse sweep, into the capture records at `base` (cap_record_bytes).
 template <int P>
 __device__ __forceinline__ void capture_row(const StepArgs &A, char *base, int q, const typename Form<P>::T (&hv)[Form<P>::V],
                                             const typename Form<P>::T (&jxv)[Form<P>::V],
                                             const typename Form<P>::T (&jyv)[Form<P>::V], const Lane<P> &L,
-                                            typename Form<P>::T href) {
+                                            typename Form<P>::T href, int x0, int xend, int lane) {
   using T = typename Form<P>::T;
-  constexpr int ES = sizeof(T);
-  const uint32_t prb = (uint32_t)(A.ldx * ES);
-  const size_t ro = (size_t)q * prb;
-  const rsrc_t c0 = make_rsrc(base + ro, prb);
-  const rsrc_t c1 = make_rsrc(base + (size_t)A.plane * ES + ro, prb);
-  const rsrc_t c2 = make_rsrc(base + 2 * (size_t)A.plane * ES + ro, prb);
+  constexpr int V = Form<P>::V, B = Form<P>::B, ES = sizeof(T);
+  constexpr int CRB = cap_record_bytes<P>(), SEG = B * ES;
+  const uint32_t rowb = (uint32_t)(A.nblk * CRB);
+  const rsrc_t row = make_rsrc(base + (size_t)q * rowb, rowb);
+  if constexpr (V == 2) {
+    if (L.pair) {
+      st_f32x2(row, L.oc[0], href + hv[0], href + hv[1]);
+      st_f32x2(row, L.oc[0] + SEG, jxv[0], jxv[1]);
+      st_f32x2(row, L.oc[0] + 2 * SEG, jyv[0], jyv[1]);
+    } else {
 #pragma unroll
-  for (int v = 0; v < Form<P>::V; ++v) {
-    if (L.out[v]) {
-      st_t(c0, L.col[v] * ES, href + hv[v]);
-      st_t(c1, L.col[v] * ES, jxv[v]);
-      st_t(c2, L.col[v] * ES, jyv[v]);
+      for (int v = 0; v < V; ++v) {
+        if (L.out[v]) {
+          st_t(row, L.oc[v], href + hv[v]);
+          st_t(row, L.oc[v] + SEG, jxv[v]);
+          st_t(row, L.oc[v] + 2 * SEG, jyv[v]);
+        }
+      }
+    }
+  } else {
+    if (L.out[0]) {
+      st_t(row, L.oc[0], href + hv[0]);
+      st_t(row, L.oc[0] + SEG, jxv[0]);
+      st_t(row, L.oc[0] + 2 * SEG, jyv[0]);
     }
   }
+  // zero the padding of a full record so that its last line is written whole
+  if (xend - x0 == B && 4 * lane < CRB - 3 * SEG) st_f32(row, (x0 / B) * CRB + 3 * SEG + 4 * lane, 0.f);
 }
 
 // NS fused time steps per pass (1 or 2).  Stage 0 consumes the stored rows;
@@ -463,7 +478,7 @@ __device__ __forceinline__ void capture_row(const StepArgs &A, char *base, int q
 // values of rows q-1, q, q+1), whose output is stored.  The strip's chunk
 // reads 2 + 3 (NS - 1) halo rows above and below.  With CAP the moments of
 // each step's pre-collision state on the tile's own rows go to the capture:
-// step t at A.capture, step t + 1 one capture block (3 planes) later.
+// step t at A.capture, step t + 1 one capture block later.
 template <int P, bool KF, bool CAP, int NS>
 __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   using T = typename Form<P>::T;
@@ -498,6 +513,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
     const int blk = L.col[v] / B;
     const int pos = L.col[v] - blk * B;
     L.oe[v] = blk * RB + pos * ES;
+    L.oc[v] = blk * cap_record_bytes<P>() + pos * ES;
     L.o16[v] = blk * RB + pos * 2;
     L.out[v] = (a + v >= x0) && (a + v < xend);
   }
@@ -547,13 +563,13 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
       const int q = y0 - HALO + k - 2;  // row of the post-collision values (unwrapped)
       if constexpr (NS == 1) {
         store_row<P>(A, q, post, hv, L, x0, xend, lane);
-        if constexpr (CAP) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href);
+        if constexpr (CAP) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane);
       } else {
         // row q - 1 of the next step is complete: c_ly = +1 populations from
         // row q - 2, c_ly = 0 from row q - 1, c_ly = -1 from row q
         const int e = k - 4;  // emission index; q = y0 - 3 + e
         if constexpr (CAP) {
-          if (q >= y0 && q < yend) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href);
+          if (q >= y0 && q < yend) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane);
         }
         if constexpr (P == kF16S) fp16s_roundtrip<V>(post, hv, A);  // as if stored and reloaded
         T g[9][V];
@@ -586,7 +602,9 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
           T post2[9][V], hv2[V], jx2[V], jy2[V];
           if (S1.finish(j, g2, post2, hv2, jx2, jy2, C, L, bad)) {
             store_row<P>(A, y0 - 4 + j, post2, hv2, L, x0, xend, lane);
-            if constexpr (CAP) capture_row<P>(A, A.capture + 3 * A.plane * ES, y0 - 4 + j, hv2, jx2, jy2, L, C.href);
+            if constexpr (CAP)
+              capture_row<P>(A, A.capture + (size_t)ny * A.nblk * cap_record_bytes<P>(), y0 - 4 + j, hv2, jx2, jy2, L,
+                             C.href, x0, xend, lane);
           }
         }
       }
@@ -764,6 +782,9 @@ int step_blocks_per_cu(int prec, bool kf, int ns) {
 }
 
 int record_sites(int prec) { return prec == kF64 ? Form<kF64>::B : (prec == kF32 ? Form<kF32>::B : Form<kF16S>::B); }
+int capture_record_bytes(int prec) {
+  return prec == kF64 ? cap_record_bytes<kF64>() : (prec == kF32 ? cap_record_bytes<kF32>() : cap_record_bytes<kF16S>());
+}
 int record_bytes(int prec) {
   return prec == kF64 ? Form<kF64>::RB : (prec == kF32 ? Form<kF32>::RB : Form<kF16S>::RB);
 }

@@ -10,6 +10,7 @@ namespace tflbm {
 // Sites per population record (= output columns of one marching strip) and
 // bytes per record, for a storage form.
 int record_sites(int prec);
+int capture_record_bytes(int prec);
 // Workgroups of the term-balance diagnostic and its launcher (partial: 8 x nb doubles).
 int terms_blocks(int nx, int ny, int max_blocks);
 hipError_t launch_terms(int prec, const StepArgs &A, bool kfield, double *partial, int nb, double *out, hipStream_t s);

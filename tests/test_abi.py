@@ -90,7 +90,8 @@ def test_workspace_and_state_sizes(lib, prec, per_site):
     assert RB >= per_site * B
     assert lib.tflbm_workspace_bytes(h) >= 2 * 30 * nblk * RB
     wb = 8 if prec == 0 else 4
-    assert lib.tflbm_capture_bytes(h) == 3 * wb * ldx * 30
+    # capture: records of the same B columns, three segments padded to whole lines
+    assert lib.tflbm_capture_bytes(h) == 30 * nblk * (-(-3 * B * wb // 128) * 128)
     assert lib.tflbm_adj_bytes(h) >= 2 * 9 * wb * ldx * 30 + 8 * ldx * 30
     lib.tflbm_destroy(h)
 
