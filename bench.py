@@ -120,6 +120,45 @@ def adjoint_ratio(prec="fp32", n=512, steps=4096, K=64):
             "checkpoint_every": K, "storage": prec}
 
 
+def reverse_sweep_at(n, K=16):
+    """Per-step times of the pieces of the backward pass at n x n (the dewetting
+    recipe, FP32): forward step, recompute with capture, adjoint step; and the
+    backward/forward ratio they give (checkpoint copies excluded)."""
+    import ctypes
+    import torch
+    from paper_1810_07642_amd import Sim, inputs
+    p, h0, th = inputs.patterned_dewetting(n=n)
+    sim = Sim(n, n, "fp32", href=0.1, **p).init(h0, th)
+    cb = sim.capture_bytes()
+    cap = torch.empty(K * cb, dtype=torch.uint8, device="cuda")
+    adj = torch.zeros(sim.adj_bytes(), dtype=torch.uint8, device="cuda")
+    sim.adj_seed(adj, torch.zeros(n, n, dtype=torch.float64))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / K
+
+    def adjoint():
+        for t in range(K - 1, -1, -1):
+            sim.lib.tflbm_adj_step(sim.h, ctypes.c_void_p(adj.data_ptr()), ctypes.c_void_p(cap.data_ptr() + t * cb),
+                                   sim.stream)
+
+    f = timed(lambda: sim.step(K))
+    c = timed(lambda: sim.step_capture(K, cap))
+    a = timed(adjoint)
+    del sim, cap, adj
+    torch.cuda.empty_cache()
+    return {"grid": n, "forward_us_per_step": round(f * 1e3, 1), "capture_us_per_step": round(c * 1e3, 1),
+            "adjoint_us_per_step": round(a * 1e3, 1), "ratio": round((c + a) / f, 3),
+            "adjoint_GBps_at_104B_per_site": round(104 * n * n / (a * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(p, h0, th, budget_s=12.0):
     """The FP64 oracle (never tuned) on the host cores: whole steps of the same
     4096 x 4096 workload until ~budget_s of CPU work, at least two."""
@@ -249,6 +288,7 @@ def main():
         del h16, h64ref
         torch.cuda.empty_cache()
         extras["adjoint"] = adjoint_ratio()
+        extras["reverse_sweep_at_headline_size"] = reverse_sweep_at(n)
         line["extras"] = extras
         log(f"fp64 {mlups64:.0f} MLUPS, fp16s {mlups16:.0f} MLUPS, adjoint/forward {extras['adjoint']['ratio']:.2f}")
 
