@@ -80,6 +80,23 @@ def test_fp32_matches_oracle(case):
     assert err <= fp32_tol(steps)
 
 
+@pytest.mark.parametrize("n,m", [(2, 3), (3, 6), (4, 10), (10, 4), (3, 9)])
+def test_other_disjoining_exponents_match_oracle(n, m):
+    """The exponent pairs the paper names besides (9, 3) (Sec. II, after eq.
+    "disjoiningP"), in either order, on the general power path of the kernel:
+    FP64 within 1e-12, FP32 within its bound."""
+    ny, nx, steps = 40, 130, 80
+    p = dict(tau=0.9, gamma=0.01, g=1e-3, hstar=0.2, delta=1.0, ax=1e-5, n=n, m=m)
+    h0, th = random_case(ny, nx, 300 + 10 * n + m)
+    ho, uxo, _, mo = oracle_run(p, h0, th, steps)
+    hg, uxg, _, mg = gpu_run(p, h0, th, steps, "fp64")
+    assert max_rel(hg, ho) <= TOL64
+    assert max_rel(uxg, uxo) <= TOL64 * 10
+    assert abs(mg - mo) <= 1e-13 * abs(mo)
+    hg, _, _, _ = gpu_run(p, h0, th, steps, "fp32", href=0.45)
+    assert max_rel(hg, ho) <= fp32_tol(steps)
+
+
 @pytest.mark.parametrize("case", [0, 2, 3])
 def test_reference_height_fp64_and_fp32_match_oracle(case):
     """Storage as deviations from E_l(href) is the same map: FP64 within
