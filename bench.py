@@ -40,9 +40,17 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the step kernel's source code with comments and blank lines
+    removed, so that the committed counter summary stays valid across edits
+    of comments only."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        h.update(open(p, "rb").read())
+        text = open(p).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

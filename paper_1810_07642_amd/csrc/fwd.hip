@@ -10,18 +10,19 @@
 // neighbour's value), so every lane stores exactly its own columns and every
 // store of a wavefront covers whole 128-byte lines of a record.
 //
-// Fused step: one wavefront owns one record column (B output columns) plus a
-// halo of (64 V - B)/2 columns per side, and a chunk of H rows, and marches
-// down the rows.  Per row it reads the nine segments of the row's records
-// (coalesced, prefetched two rows ahead), assembles the populations of its
-// own columns (x shift through a cross-lane move), forms h; one row later the
-// film pressure of the previous row (Laplacian of h and disjoining term); one
-// more row later the isotropic pressure gradient, forces, equilibrium and
-// collision of the row two above, whose populations were parked in LDS, and
-// stores them.  Stencil neighbours in x come from adjacent lanes; the
-// three-row windows of h and p stay in registers.  HBM sees each record read
-// once and written once per step; the halo columns and the four halo rows of
-// a chunk are re-read from L2.
+// Step kernel: one wavefront owns one record column (B output columns) plus a
+// halo of (64 V - B)/2 = 6 columns per side, and a chunk of H rows, and
+// marches down the rows.  Per row it reads the nine segments of the row's
+// records (coalesced, prefetched two rows ahead), assembles the deviations of
+// its own columns (x shift through a cross-lane move), forms dh; one row later
+// the film pressure of the previous row (Laplacian and disjoining term), kept
+// as its x difference and x-smoothed value; one more row later the isotropic
+// pressure gradient, forces, equilibrium and collision of the row two above,
+// whose populations were parked in LDS, and stores them.  Stencil neighbours
+// in x come from adjacent lanes; no barriers.  With two fused steps a second
+// such stage consumes the first one's output rows in registers, so every
+// record crosses HBM once per two steps; the halo columns and the ten halo
+// rows of a chunk are re-read (partly from L2).
 #include <type_traits>
 
 #include "device.h"
