@@ -130,8 +130,13 @@ def adjoint_ratio(prec="fp32", n=512, steps=4096, K=64):
 
 def reverse_sweep_at(n, K=16):
     """Per-step times of the pieces of the backward pass at n x n (the dewetting
-    recipe, FP32): forward step, recompute with capture, adjoint step; and the
-    backward/forward ratio they give (checkpoint copies excluded)."""
+    recipe, FP32): forward step, recompute with capture, and the adjoint, both
+    two steps per pass (tflbm_adj_steps, what the backward pass runs) and one
+    step per pass (tflbm_adj_step); the backward/forward ratio they give
+    (checkpoint copies excluded).  Algorithmic bytes per site and step: 104
+    one step per pass (adjoint read and write 36 + 36, h and j 12, kappa 4,
+    FP64 g_kappa read and write 16), 58 two steps per pass (116 per pass:
+    two captures, one adjoint read and write, one g_kappa update)."""
     import ctypes
     import torch
     from paper_1810_07642_amd import Sim, inputs
@@ -152,19 +157,23 @@ def reverse_sweep_at(n, K=16):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / K
 
-    def adjoint():
+    def adjoint_single():
         for t in range(K - 1, -1, -1):
             sim.lib.tflbm_adj_step(sim.h, ctypes.c_void_p(adj.data_ptr()), ctypes.c_void_p(cap.data_ptr() + t * cb),
                                    sim.stream)
 
     f = timed(lambda: sim.step(K))
     c = timed(lambda: sim.step_capture(K, cap))
-    a = timed(adjoint)
+    a2 = timed(lambda: sim.adj_steps(adj, cap, K))
+    a1 = timed(adjoint_single)
     del sim, cap, adj
     torch.cuda.empty_cache()
     return {"grid": n, "forward_us_per_step": round(f * 1e3, 1), "capture_us_per_step": round(c * 1e3, 1),
-            "adjoint_us_per_step": round(a * 1e3, 1), "ratio": round((c + a) / f, 3),
-            "adjoint_GBps_at_104B_per_site": round(104 * n * n / (a * 1e-3) / 1e9, 1)}
+            "adjoint_us_per_step": round(a2 * 1e3, 1), "ratio": round((c + a2) / f, 3),
+            "adjoint_GBps_at_58B_per_site": round(58 * n * n / (a2 * 1e-3) / 1e9, 1),
+            "adjoint_one_step_per_pass_us_per_step": round(a1 * 1e3, 1),
+            "ratio_one_step_per_pass": round((c + a1) / f, 3),
+            "adjoint_one_step_per_pass_GBps_at_104B_per_site": round(104 * n * n / (a1 * 1e-3) / 1e9, 1)}
 
 
 def fp64_by_lattice(mlups_4096):

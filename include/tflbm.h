@@ -186,7 +186,8 @@ int tflbm_state_load(tflbm_sim *sim, const void *d_src, int64_t step, tflbm_stre
  * loss whose gradient with respect to the final height is given.  Use:
  *   seed with dL/dh_N; then for each step t = N-1 ... 0, in that order, call
  *   tflbm_adj_step with the capture of step t (the moments at the start of
- *   step t, written by tflbm_step_capture); then tflbm_adj_finish.
+ *   step t, written by tflbm_step_capture), or tflbm_adj_steps once per
+ *   captured segment; then tflbm_adj_finish.
  * The adjoint state is stored in the working precision (FP64 for
  * TFLBM_FP64, FP32 otherwise); the kappa gradient accumulates in FP64. */
 
@@ -212,6 +213,17 @@ int tflbm_adj_seed(tflbm_sim *sim, void *d_adj, const double *d_grad_h, tflbm_st
  * capture of step t (d_capture_t, tflbm_capture_bytes bytes), and adds the
  * step's contribution to the kappa gradient. */
 int tflbm_adj_step(tflbm_sim *sim, void *d_adj, const void *d_capture_t, tflbm_stream_t stream);
+
+/* (async) The reverse pass over one captured segment: tflbm_adj_step for
+ * t = nsteps-1 down to 0 with the capture of step t at
+ * d_capture + t * tflbm_capture_bytes (the layout tflbm_step_capture writes;
+ * nsteps captures must be there).  On lattices that fill the GPU, two
+ * steps run per pass over the lattice, the adjoint of step t feeding that of
+ * step t-1 on chip, which halves the adjoint and kappa-gradient traffic; on
+ * smaller ones the steps run singly.  The result is bit for bit that of the
+ * single steps either way.  nsteps = 0 does nothing; EINVAL for nsteps < 0 or
+ * a NULL pointer, ESTATE before tflbm_adj_seed. */
+int tflbm_adj_steps(tflbm_sim *sim, void *d_adj, const void *d_capture, int64_t nsteps, tflbm_stream_t stream);
 
 /* (async) dL/dh0 = sum_l lambda_l dE_l/dh0 and dL/dtheta = dL/dkappa dkappa/dtheta.
  * d_h0: the initial height used by tflbm_init; d_theta: its theta field, or

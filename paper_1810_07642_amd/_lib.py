@@ -63,6 +63,7 @@ SIGNATURES = {
     "tflbm_adj_bytes": (_sz, [_vp]),
     "tflbm_adj_seed": (_int, [_vp, _vp, _dp, _vp]),
     "tflbm_adj_step": (_int, [_vp, _vp, _vp, _vp]),
+    "tflbm_adj_steps": (_int, [_vp, _vp, _vp, ctypes.c_int64, _vp]),
     "tflbm_adj_finish": (_int, [_vp, _vp, _dp, _dp, _dp, _dp, _vp]),
 }
 

@@ -4,7 +4,8 @@ Forward: f = E(h0), kappa(theta), then `nsteps` HIP steps, storing the
 population buffer every K steps; returns the final height h_N.
 Backward: for each K-step segment, last to first, reload its checkpoint,
 recompute the segment with the forward moments captured at every step, and
-run the hand-written adjoint step backwards through it; finally map the
+run the hand-written adjoint backwards through it (two steps per pass over
+the lattice); finally map the
 adjoint of the initial populations and the FP64 kappa gradient to
 dLoss/dh0 and dLoss/dtheta.  Memory: nsteps/K checkpoints plus K captures.
 """
@@ -46,8 +47,7 @@ class TFLBMRun(torch.autograd.Function):
         for buf, start, k in reversed(ctx.ckpts):
             sim.state_load(buf, start)
             sim.step_capture(k, cap)
-            for i in reversed(range(k)):
-                sim.adj_step(adj, cap[i * cb:(i + 1) * cb])
+            sim.adj_steps(adj, cap, k)
         g_h0, g_theta = sim.adj_finish(adj)
         ctx.sim = None
         ctx.ckpts = None

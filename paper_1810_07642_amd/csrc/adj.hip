@@ -35,6 +35,7 @@ struct AdjArgs {
   const char *src;     // mu at the end of step t: [9][ny][ldx] in T
   char *dst;           // mu at the end of step t-1
   const char *cap;     // h, jx, jy of step t: capture records of the forward form
+  const char *cap2;    // the same for step t-1 (two-step pass only)
   const void *kfield;  // kappa [ny][ldx] in T or nullptr
   double *gk;          // dLoss/dkappa [ny][ldx] FP64
   int nx, ny, ldx;
@@ -45,7 +46,8 @@ struct AdjArgs {
   double omega, gamma, nu, hstar, delta, ax, ay, g, kappa0;
 };
 
-constexpr int kAdjOutW = 60;  // 64 lanes, one column each, two halo columns per side
+constexpr int kAdjOutW = 60;   // one step: 64 lanes, one column each, two halo columns per side
+constexpr int kAdj2OutW = 54;  // two steps: five halo columns per side
 
 // The forward form whose capture records the reverse step reads (FP32 and
 // FP16S share the record geometry).
@@ -58,7 +60,7 @@ template <> struct CapForm<float> {
   static_assert(Form<kF16S>::B == Form<kF32>::B && cap_record_bytes<kF16S>() == cap_record_bytes<kF32>(),
                 "FP32 and FP16S capture records must agree");
 };
-int adj_columns_per_strip() { return kAdjOutW; }
+int adj_columns_per_strip(int ns) { return ns == 2 ? kAdj2OutW : kAdjOutW; }
 
 // Lambda_F = 3 sum_l w_l c_l mu_l through differences of opposite populations.
 template <typename T>
@@ -81,6 +83,174 @@ template <typename T> __device__ __forceinline__ void powers(T r, int n, int m, 
   }
 }
 
+// Scalar coefficients of the reverse step in the working type.
+template <typename T> struct AdjCoef {
+  T omega, om1, gamma, nu, hstar, delta, three_d2, ax, ay, g, kap0, cA, cD;
+  int n_exp, m_exp;
+  __device__ explicit AdjCoef(const AdjArgs &A)
+      : omega((T)A.omega), om1(T(1) - (T)A.omega), gamma((T)A.gamma), nu((T)A.nu), hstar((T)A.hstar),
+        delta((T)A.delta), three_d2(T(3) * (T)A.delta * (T)A.delta), ax((T)A.ax), ay((T)A.ay), g((T)A.g),
+        kap0((T)A.kappa0), cA((T)(3.0 * kW[1])), cD((T)(3.0 * kW[2])), n_exp(A.n_exp), m_exp(A.m_exp) {}
+};
+
+// h, j_x, j_y of one column, read from the capture records of a forward step.
+template <typename T> struct CapReader {
+  static constexpr int SEG = CapForm<T>::B * (int)sizeof(T);
+  const char *base;
+  size_t row_bytes;
+  __device__ CapReader(const char *cap, int cnblk, int col)
+      : base(cap + (size_t)(col / CapForm<T>::B) * CapForm<T>::CRB + (size_t)(col % CapForm<T>::B) * sizeof(T)),
+        row_bytes((size_t)cnblk * CapForm<T>::CRB) {}
+  __device__ __forceinline__ void read(int row, T &h, T &jx, T &jy) const {
+    const char *p = base + (size_t)row * row_bytes;
+    h = *(const T *)p;
+    jx = *(const T *)(p + SEG);
+    jy = *(const T *)(p + 2 * SEG);
+  }
+};
+
+// One reverse step as a machine over the rows of a strip, one column per
+// lane.  Rows enter in increasing y.  Once row r has entered (`push`), the
+// stage has formed the film pressure and lambda_p of row r-1, and `out` gives
+// the adjoint populations of row r-2.  The x stencils read the neighbouring
+// lanes, so the first and last two lanes of the strip are halo.  Row indices
+// count from the newest: 0 = r, 1 = r-1, 2 = r-2, 3 = r-3.  Both x-stencils
+// of a row are folded into two numbers per quantity at the row's entry
+// (the difference and the weighted sum of its left and right neighbours), so
+// that the rows kept in flight are single values.
+template <typename T> struct AdjStage {
+  T h0 = 0, h1 = 0, h2 = 0;                               // h
+  T s0 = 0, s1 = 0, s2 = 0;                               // h(x-1) + h(x+1)
+  T jx0 = 0, jx1 = 0, jx2 = 0, jy0 = 0, jy1 = 0, jy2 = 0;  // j
+  T k0 = 0, k1 = 0, k2 = 0;                               // kappa
+  T Fx0 = 0, Fx1 = 0, Fx2 = 0, Fy0 = 0, Fy1 = 0, Fy2 = 0;  // Lambda_F
+  T ga0 = 0, ga1 = 0, ga2 = 0;   // lambda_Gx(x+1) - lambda_Gx(x-1)
+  T gb0 = 0, gb1 = 0, gb2 = 0;   // cA lambda_Gy(x) + cD (lambda_Gy(x-1) + lambda_Gy(x+1))
+  T pa1 = 0, pa2 = 0, pa3 = 0;   // p(x+1) - p(x-1)
+  T pb1 = 0, pb2 = 0, pb3 = 0;   // cA p(x) + cD (p(x-1) + p(x+1))
+  T q1 = 0, q2 = 0, q3 = 0;      // lambda_p
+  T qs1 = 0, qs2 = 0, qs3 = 0;   // lambda_p(x-1) + lambda_p(x+1)
+  T ih1 = 0, ih2 = 0, rn1 = 0, rn2 = 0, rm1 = 0, rm2 = 0;  // 1/h, (h_*/h)^n, (h_*/h)^m
+
+  // Row r enters with its pre-shifted adjoint mu and the forward h, j and
+  // kappa; `full` = rows r-1 and r-2 entered before it.
+  __device__ __forceinline__ void push(const T (&mu)[9], T h, T jx, T jy, T kap, bool full, const AdjCoef<T> &C) {
+    h2 = h1; h1 = h0; h0 = h;
+    s2 = s1; s1 = s0; s0 = from_left(h) + from_right(h);
+    jx2 = jx1; jx1 = jx0; jx0 = jx;
+    jy2 = jy1; jy1 = jy0; jy0 = jy;
+    k2 = k1; k1 = k0; k0 = kap;
+    Fx2 = Fx1; Fx1 = Fx0;
+    Fy2 = Fy1; Fy1 = Fy0;
+    lambda_force(mu, C.cA, C.cD, Fx0, Fy0);
+    // lambda_G = -h Lambda_F, kept as the two combinations its divergence reads
+    const T gx = -h * Fx0, gy = -h * Fy0;
+    ga2 = ga1; ga1 = ga0; ga0 = from_right(gx) - from_left(gx);
+    gb2 = gb1; gb1 = gb0; gb0 = madd(C.cA, gy, C.cD * (from_left(gy) + from_right(gy)));
+    if (!full) return;
+    // forward film pressure of row r-1 (Laplacian over rows r-2 .. r)
+    const T lap = (T(4) * ((s1 + h0) + h2) + (s0 + s2) - T(20) * h1) * T(1.0 / 6.0);
+    ih2 = ih1; rn2 = rn1; rm2 = rm1;
+    ih1 = recip(h1);
+    powers(C.hstar * ih1, C.n_exp, C.m_exp, rn1, rm1);
+    const T p = -C.gamma * (lap + k1 * (rn1 - rm1));
+    pa3 = pa2; pa2 = pa1; pa1 = from_right(p) - from_left(p);
+    pb3 = pb2; pb2 = pb1; pb1 = madd(C.cA, p, C.cD * (from_left(p) + from_right(p)));
+    // lambda_p of row r-1 = -div_s lambda_G (lambda_G rows r-2 .. r)
+    const T q = -(madd(C.cA, ga1, C.cD * (ga0 + ga2)) + (gb0 - gb2));
+    q3 = q2; q2 = q1; q1 = q;
+    qs3 = qs2; qs2 = qs1; qs1 = from_left(q) + from_right(q);
+  }
+
+  // Adjoint populations lambda^t_l of row r-2 from that row's mu, and the
+  // row's term -gamma phi(h) lambda_p of dLoss/dkappa.
+  __device__ __forceinline__ void out(const T (&mu)[9], T (&lam)[9], double &gterm, const AdjCoef<T> &C) const {
+    const T h = h2, inv_h = ih2;
+    const T ux = jx2 * inv_h, uy = jy2 * inv_h;
+    // forward pressure gradient (p rows r-3 .. r-1)
+    const T Gx = madd(C.cA, pa2, C.cD * (pa1 + pa3));
+    const T Gy = pb1 - pb3;
+    // Laplacian of lambda_p (rows r-3 .. r-1)
+    const T lapq = (T(4) * ((qs2 + q1) + q3) + (qs1 + qs3) - T(20) * q2) * T(1.0 / 6.0);
+    const T lp = q2;
+
+    const T invD = recip(madd(T(2) * h, h, madd(T(6) * C.delta, h, C.three_d2)));
+    const T alpha = T(6) * h * invD;
+    const T dalpha = T(6) * madd(T(-2) * h, h, C.three_d2) * (invD * invD);
+    const T phi = rn2 - rm2;
+    const T dphi = (T(C.m_exp) * rm2 - T(C.n_exp) * rn2) * inv_h;
+
+    // omega sum_l mu_l dfeq_l/dh and omega sum_l mu_l dfeq_l/du over pairs
+    // of opposite populations: S = mu_l + mu_-l takes the parts of the
+    // derivatives even in c, D = mu_l - mu_-l the odd ones
+    const T usq = madd(ux, ux, uy * uy);
+    const T gh = C.g * h;
+    const T up = ux + uy, um = uy - ux;
+    const T S15 = mu[1] + mu[5], D15 = mu[1] - mu[5];
+    const T S37 = mu[3] + mu[7], D37 = mu[3] - mu[7];
+    const T S26 = mu[2] + mu[6], D26 = mu[2] - mu[6];
+    const T S48 = mu[4] + mu[8], D48 = mu[4] - mu[8];
+    // d/dh: rest 1 - 5gh/3 - 2u^2/3; axes gh/3 + cu/3 + cu^2/2 - u^2/6;
+    // diagonals gh/12 + cu/12 + cu^2/8 - u^2/24
+    T sh = mu[0] * madd(gh, T(-5.0 / 3.0), madd(usq, T(-2.0 / 3.0), T(1)));
+    sh = madd(S15 + S37, madd(gh, T(1.0 / 3.0), usq * T(-1.0 / 6.0)), sh);
+    sh = madd(T(0.5), madd(S15, ux * ux, S37 * (uy * uy)), sh);
+    sh = madd(T(1.0 / 3.0), madd(D15, ux, D37 * uy), sh);
+    sh = madd(S26 + S48, madd(gh, T(1.0 / 12.0), usq * T(-1.0 / 24.0)), sh);
+    sh = madd(T(0.125), madd(S26, up * up, S48 * (um * um)), sh);
+    sh = madd(T(1.0 / 12.0), madd(D26, up, D48 * um), sh);
+    // d/du = h (c1 c + c2 (c.u) c - c3 u): rest -4u/3; axes (1/3, 1, 1/3);
+    // diagonals (1/12, 1/4, 1/12)
+    T sx = mu[0] * ux * T(-4.0 / 3.0);
+    sx = madd(D15, T(1.0 / 3.0), sx);
+    sx = madd(S15 - T(0.5) * S37, ux * T(2.0 / 3.0), sx);
+    sx = madd(D26 - D48, T(1.0 / 12.0), sx);
+    sx = madd(S26, madd(up, T(0.25), ux * T(-1.0 / 12.0)), sx);
+    sx = madd(S48, madd(um, T(-0.25), ux * T(-1.0 / 12.0)), sx);
+    T sy = mu[0] * uy * T(-4.0 / 3.0);
+    sy = madd(D37, T(1.0 / 3.0), sy);
+    sy = madd(S37 - T(0.5) * S15, uy * T(2.0 / 3.0), sy);
+    sy = madd(D26 + D48, T(1.0 / 12.0), sy);
+    sy = madd(S26, madd(up, T(0.25), uy * T(-1.0 / 12.0)), sy);
+    sy = madd(S48, madd(um, T(0.25), uy * T(-1.0 / 12.0)), sy);
+    const T fric = C.nu * alpha;
+    const T lux = madd(C.omega * h, sx, -fric * Fx2);
+    const T luy = madd(C.omega * h, sy, -fric * Fy2);
+    T lh = C.omega * sh + Fx2 * (-Gx - C.nu * dalpha * ux + C.ax) + Fy2 * (-Gy - C.nu * dalpha * uy + C.ay) -
+           C.gamma * lapq - C.gamma * k2 * dphi * lp;
+    lh -= (lux * ux + luy * uy) * inv_h;
+    const T ljx = lux * inv_h, ljy = luy * inv_h;
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      const int cx = kCx[l], cy = kCy[l];
+      const T cl = cx == 0 ? (cy == 0 ? T(0) : (cy > 0 ? ljy : -ljy))
+                           : (cy == 0 ? (cx > 0 ? ljx : -ljx)
+                                      : (cx > 0 ? (cy > 0 ? ljx + ljy : ljx - ljy) : (cy > 0 ? ljy - ljx : -ljx - ljy)));
+      lam[l] = madd(C.om1, mu[l], lh + cl);
+    }
+    gterm = -(double)C.gamma * (double)phi * (double)lp;
+  }
+};
+
+// Stores lambda^t_l of site (col, y) at (x - c_l, y - c_l), the pre-shifted
+// adjoint of the step before.
+template <typename T>
+__device__ __forceinline__ void store_pushed(const AdjArgs &A, int y, int col, int colW, int colE, const T (&lam)[9]) {
+  const int yN = (y + 1 == A.ny) ? 0 : y + 1;
+  const int yS = (y == 0) ? A.ny - 1 : y - 1;
+  T *dst = (T *)A.dst;
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    const int cx = kCx[l], cy = kCy[l];
+    const int yd = cy == 0 ? y : (cy > 0 ? yS : yN);
+    const int xd = cx == 0 ? col : (cx > 0 ? colW : colE);
+    dst[(size_t)l * A.plane + (size_t)yd * A.ldx + xd] = lam[l];
+  }
+}
+
+// One reverse step.  A workgroup is one wavefront marching down a strip of
+// kAdjOutW columns (plus two halo columns per side) over a chunk of rows; it
+// reads rows y0-2 .. yend+1 and writes rows y0 .. yend-1.
 template <typename T, bool KF>
 __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
   const int b = blockIdx.x;
@@ -100,30 +270,12 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
   const int col = wrap(a, nx), colE = wrap(a + 1, nx), colW = wrap(a - 1, nx);
   const bool out = (a >= x0) && (a < xend);
 
-  const T omega = (T)A.omega, gamma = (T)A.gamma, nu = (T)A.nu, hstar = (T)A.hstar;
-  const T delta = (T)A.delta, ax = (T)A.ax, ay = (T)A.ay, g = (T)A.g, kap0 = (T)A.kappa0;
-  const T cA = (T)(3.0 * kW[1]), cD = (T)(3.0 * kW[2]);
-  const int n_exp = A.n_exp, m_exp = A.m_exp;
+  const AdjCoef<T> C(A);
+  const CapReader<T> cap(A.cap, A.cnblk, col);
   const T *mu_src = (const T *)A.src;
-  // byte offset of this lane's column in a row of capture records
-  constexpr int CB = CapForm<T>::B, CRB = CapForm<T>::CRB, CSEG = CB * (int)sizeof(T);
-  const int crec = (col / CB) * CRB + (col % CB) * (int)sizeof(T);
-  const size_t crow = (size_t)A.cnblk * CRB;
-
-  // rolling rows: index 0 = row r (newest), 1 = r-1, 2 = r-2
-  T mu0[9], mu1[9], mu2[9], mun[9];
-  T hC0, hC1, hC2, hL0, hL1, hL2, hR0, hR1, hR2;        // h with left/right neighbours
-  T jx0 = 0, jx1 = 0, jx2 = 0, jy0 = 0, jy1 = 0, jy2 = 0;
-  T hn, jxn, jyn, kn = 0, k0 = 0, k1 = 0, k2 = 0;
-  T LFx0 = 0, LFy0 = 0, LFx1 = 0, LFy1 = 0, LFx2 = 0, LFy2 = 0;  // Lambda_F of rows r, r-1, r-2
-  T gxC0, gxL0, gxR0, gyC0, gyL0, gyR0;                  // lambda_G of rows r, r-1, r-2
-  T gxC1, gxL1, gxR1, gyC1, gyL1, gyR1;
-  T gxC2, gxL2, gxR2, gyC2, gyL2, gyR2;
-  T pC1 = 0, pL1 = 0, pR1 = 0, pC2 = 0, pL2 = 0, pR2 = 0, pC3 = 0, pL3 = 0, pR3 = 0;   // p rows r-1, r-2, r-3
-  T qC1 = 0, qL1 = 0, qR1 = 0, qC2 = 0, qL2 = 0, qR2 = 0, qC3 = 0, qL3 = 0, qR3 = 0;   // lambda_p rows r-1, r-2, r-3
-  hC1 = hL1 = hR1 = hC2 = hL2 = hR2 = 0;
-  gxC1 = gxL1 = gxR1 = gyC1 = gyL1 = gyR1 = 0;
-  gxC2 = gxL2 = gxR2 = gyC2 = gyL2 = gyR2 = 0;
+  AdjStage<T> S;
+  T mu1[9], mu2[9], mun[9];
+  T hn, jxn, jyn, kn = C.kap0;
 #pragma unroll
   for (int l = 0; l < 9; ++l) mu1[l] = mu2[l] = 0;
 
@@ -133,166 +285,159 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
     const size_t o = (size_t)row * ldx + col;
 #pragma unroll
     for (int l = 0; l < 9; ++l) mun[l] = mu_src[(size_t)l * plane + o];
-    const char *cr = A.cap + (size_t)row * crow + crec;
-    hn = *(const T *)cr;
-    jxn = *(const T *)(cr + CSEG);
-    jyn = *(const T *)(cr + 2 * CSEG);
+    cap.read(row, hn, jxn, jyn);
     if constexpr (KF) kn = ((const T *)A.kfield)[o];
   };
   load_row(ry);
 
   for (int k = 0; k < K; ++k) {
+    T mu0[9];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) mu0[l] = mun[l];
+    const T h = hn, jx = jxn, jy = jyn, kap = kn;
+    const int rn = (ry + 1 == ny) ? 0 : ry + 1;
+    if (k + 1 < K) load_row(rn);
+    S.push(mu0, h, jx, jy, kap, k >= 2, C);
+    if (k >= 4 && out) {
+      // output row y = r-2
+      const int y = y0 + (k - 4);
+      T lam[9];
+      double gt;
+      S.out(mu2, lam, gt, C);
+      store_pushed(A, y, col, colW, colE, lam);
+      A.gk[(size_t)y * ldx + col] += gt;
+    }
 #pragma unroll
     for (int l = 0; l < 9; ++l) {
       mu2[l] = mu1[l];
       mu1[l] = mu0[l];
-      mu0[l] = mun[l];
-    }
-    jx2 = jx1; jx1 = jx0; jx0 = jxn;
-    jy2 = jy1; jy1 = jy0; jy0 = jyn;
-    k2 = k1; k1 = k0; k0 = KF ? kn : kap0;
-    hC2 = hC1; hL2 = hL1; hR2 = hR1;
-    hC1 = hC0; hL1 = hL0; hR1 = hR0;
-    hC0 = hn;
-    LFx2 = LFx1; LFy2 = LFy1;
-    LFx1 = LFx0; LFy1 = LFy0;
-    gxC2 = gxC1; gxL2 = gxL1; gxR2 = gxR1; gyC2 = gyC1; gyL2 = gyL1; gyR2 = gyR1;
-    gxC1 = gxC0; gxL1 = gxL0; gxR1 = gxR0; gyC1 = gyC0; gyL1 = gyL0; gyR1 = gyR0;
-    const int rn = (ry + 1 == ny) ? 0 : ry + 1;
-    if (k + 1 < K) load_row(rn);
-
-    hL0 = from_left(hC0);
-    hR0 = from_right(hC0);
-    {
-      // Lambda_F and lambda_G of row r
-      lambda_force(mu0, cA, cD, LFx0, LFy0);
-      gxC0 = -hC0 * LFx0;
-      gyC0 = -hC0 * LFy0;
-      gxL0 = from_left(gxC0);
-      gxR0 = from_right(gxC0);
-      gyL0 = from_left(gyC0);
-      gyR0 = from_right(gyC0);
-    }
-
-    if (k >= 2) {
-      // rotate p and lambda_p (rows r-1 computed now)
-      pC3 = pC2; pL3 = pL2; pR3 = pR2;
-      pC2 = pC1; pL2 = pL1; pR2 = pR1;
-      qC3 = qC2; qL3 = qL2; qR3 = qR2;
-      qC2 = qC1; qL2 = qL1; qR2 = qR1;
-      // forward film pressure of row r-1 from h rows r-2 .. r
-      const T odd = ((hR1 + hC0) + hL1) + hC2;
-      const T even = ((hR0 + hL0) + hL2) + hR2;
-      const T lap = (T(4) * odd + even - T(20) * hC1) * T(1.0 / 6.0);
-      T rn1, rm1;
-      powers(hstar * recip(hC1), n_exp, m_exp, rn1, rm1);
-      pC1 = -gamma * (lap + k1 * (rn1 - rm1));
-      pL1 = from_left(pC1);
-      pR1 = from_right(pC1);
-      // lambda_p of row r-1 = -div_s lambda_G (lambda_G rows r-2 .. r)
-      T dx = cA * gxR1;
-      dx += cD * gxR0;
-      dx -= cD * gxL0;
-      dx -= cA * gxL1;
-      dx -= cD * gxL2;
-      dx += cD * gxR2;
-      T dy = cD * gyR0;
-      dy += cA * gyC0;
-      dy += cD * gyL0;
-      dy -= cD * gyL2;
-      dy -= cA * gyC2;
-      dy -= cD * gyR2;
-      qC1 = -(dx + dy);
-      qL1 = from_left(qC1);
-      qR1 = from_right(qC1);
-    }
-
-    if (k >= 4 && out) {
-      // output row y = r-2: site quantities from row index 2
-      const int y = y0 + (k - 4);
-      const T h = hC2;
-      const T inv_h = recip(h);
-      const T ux = jx2 * inv_h, uy = jy2 * inv_h;
-      // forward pressure gradient at y (p rows r-3 .. r-1)
-      const T Gx = madd(cA, pR2 - pL2, cD * ((pR1 - pL1) + (pR3 - pL3)));
-      const T Gy = madd(cA, pC1 - pC3, cD * ((pR1 - pR3) + (pL1 - pL3)));
-      // Laplacian of lambda_p at y (lambda_p rows r-3 .. r-1)
-      const T qodd = ((qR2 + qC1) + qL2) + qC3;
-      const T qeven = ((qR1 + qL1) + qL3) + qR3;
-      const T lapq = (T(4) * qodd + qeven - T(20) * qC2) * T(1.0 / 6.0);
-      const T lp = qC2;
-
-      const T three_d2 = T(3) * delta * delta;
-      const T invD = recip(madd(T(2) * h, h, madd(T(6) * delta, h, three_d2)));
-      const T alpha = T(6) * h * invD;
-      const T dalpha = T(6) * madd(T(-2) * h, h, three_d2) * (invD * invD);
-      T rn_, rm_;
-      powers(hstar * inv_h, n_exp, m_exp, rn_, rm_);
-      const T phi = rn_ - rm_;
-      const T dphi = (T(m_exp) * rm_ - T(n_exp) * rn_) * inv_h;
-      const T LFx = LFx2, LFy = LFy2;
-
-      // omega sum_l mu_l dfeq_l/dh and omega sum_l mu_l dfeq_l/du over pairs
-      // of opposite populations: S = mu_l + mu_-l takes the parts of the
-      // derivatives even in c, D = mu_l - mu_-l the odd ones
-      const T usq = madd(ux, ux, uy * uy);
-      const T gh = g * h;
-      const T up = ux + uy, um = uy - ux;
-      const T S15 = mu2[1] + mu2[5], D15 = mu2[1] - mu2[5];
-      const T S37 = mu2[3] + mu2[7], D37 = mu2[3] - mu2[7];
-      const T S26 = mu2[2] + mu2[6], D26 = mu2[2] - mu2[6];
-      const T S48 = mu2[4] + mu2[8], D48 = mu2[4] - mu2[8];
-      // d/dh: rest 1 - 5gh/3 - 2u^2/3; axes gh/3 + cu/3 + cu^2/2 - u^2/6;
-      // diagonals gh/12 + cu/12 + cu^2/8 - u^2/24
-      T sh = mu2[0] * madd(gh, T(-5.0 / 3.0), madd(usq, T(-2.0 / 3.0), T(1)));
-      sh = madd(S15 + S37, madd(gh, T(1.0 / 3.0), usq * T(-1.0 / 6.0)), sh);
-      sh = madd(T(0.5), madd(S15, ux * ux, S37 * (uy * uy)), sh);
-      sh = madd(T(1.0 / 3.0), madd(D15, ux, D37 * uy), sh);
-      sh = madd(S26 + S48, madd(gh, T(1.0 / 12.0), usq * T(-1.0 / 24.0)), sh);
-      sh = madd(T(0.125), madd(S26, up * up, S48 * (um * um)), sh);
-      sh = madd(T(1.0 / 12.0), madd(D26, up, D48 * um), sh);
-      // d/du = h (c1 c + c2 (c.u) c - c3 u): rest -4u/3; axes (1/3, 1, 1/3);
-      // diagonals (1/12, 1/4, 1/12)
-      T sx = mu2[0] * ux * T(-4.0 / 3.0);
-      sx = madd(D15, T(1.0 / 3.0), sx);
-      sx = madd(S15 - T(0.5) * S37, ux * T(2.0 / 3.0), sx);
-      sx = madd(D26 - D48, T(1.0 / 12.0), sx);
-      sx = madd(S26, madd(up, T(0.25), ux * T(-1.0 / 12.0)), sx);
-      sx = madd(S48, madd(um, T(-0.25), ux * T(-1.0 / 12.0)), sx);
-      T sy = mu2[0] * uy * T(-4.0 / 3.0);
-      sy = madd(D37, T(1.0 / 3.0), sy);
-      sy = madd(S37 - T(0.5) * S15, uy * T(2.0 / 3.0), sy);
-      sy = madd(D26 + D48, T(1.0 / 12.0), sy);
-      sy = madd(S26, madd(up, T(0.25), uy * T(-1.0 / 12.0)), sy);
-      sy = madd(S48, madd(um, T(0.25), uy * T(-1.0 / 12.0)), sy);
-      const T fric = nu * alpha;
-      const T lux = madd(omega * h, sx, -fric * LFx);
-      const T luy = madd(omega * h, sy, -fric * LFy);
-      T lh = omega * sh + LFx * (-Gx - nu * dalpha * ux + ax) + LFy * (-Gy - nu * dalpha * uy + ay) -
-             gamma * lapq - gamma * k2 * dphi * lp;
-      lh -= (lux * ux + luy * uy) * inv_h;
-      const T ljx = lux * inv_h, ljy = luy * inv_h;
-
-      const int yN = (y + 1 == ny) ? 0 : y + 1;
-      const int yS = (y == 0) ? ny - 1 : y - 1;
-      T *dst = (T *)A.dst;
-      const T om1 = T(1) - omega;
-#pragma unroll
-      for (int l = 0; l < 9; ++l) {
-        const int cx = kCx[l], cy = kCy[l];
-        const T cl = cx == 0 ? (cy == 0 ? T(0) : (cy > 0 ? ljy : -ljy))
-                             : (cy == 0 ? (cx > 0 ? ljx : -ljx)
-                                        : (cx > 0 ? (cy > 0 ? ljx + ljy : ljx - ljy) : (cy > 0 ? ljy - ljx : -ljx - ljy)));
-        const T lam = madd(om1, mu2[l], lh + cl);
-        // store at x - c_l
-        const int yd = cy == 0 ? y : (cy > 0 ? yS : yN);
-        const int xd = cx == 0 ? col : (cx > 0 ? colW : colE);
-        dst[(size_t)l * plane + (size_t)yd * ldx + xd] = lam;
-      }
-      double *gk = A.gk + (size_t)y * ldx + col;
-      *gk += -(double)gamma * (double)phi * (double)lp;
     }
     ry = rn;
+  }
+}
+
+// Two reverse steps, t and t-1, in one pass.  The step-t stage runs as in
+// adj_step_kernel, five rows ahead of the step-(t-1) stage, and hands it its
+// adjoint through a ring of five rows in LDS: the step-(t-1) input
+// mu_l(x, y) = lambda^t_l(x + c_l, y + c_l) is read from the ring rather
+// than stored to memory and streamed back.  The step-t contribution to
+// dLoss/dkappa waits in a second ring until the step-(t-1) stage reaches the
+// same row, so that g_kappa is read and written once per pass and receives
+// the two terms in the order of two single steps.  The workgroup is a single
+// wavefront, so the ring needs no barrier between wavefronts.  Strips are
+// kAdj2OutW columns plus five halo columns per side (two per stage plus the
+// one-column shift between them); rows y0-5 .. yend+4 are read.
+template <typename T, bool KF>
+__global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
+  __shared__ T ring[5][9][64];
+  __shared__ double gring[4][64];
+  const int b = blockIdx.x;
+  const int tile = (b & 7) * A.per_xcd + (b >> 3);
+  if (tile >= A.ntiles) return;
+  const int strip = tile % A.nstrips;
+  const int chunk = tile / A.nstrips;
+  const int x0 = strip * kAdj2OutW;
+  const int y0 = chunk * A.H;
+  const int yend = min(y0 + A.H, A.ny);
+  const int xend = min(x0 + kAdj2OutW, A.nx);
+  const int lane = threadIdx.x;
+  const int nx = A.nx, ny = A.ny, ldx = A.ldx;
+  const int64_t plane = A.plane;
+
+  const int a = x0 - 5 + lane;
+  const int col = wrap(a, nx), colE = wrap(a + 1, nx), colW = wrap(a - 1, nx);
+  const bool out = (a >= x0) && (a < xend);
+  // ring columns of x - 1 and x + 1 (the end lanes read themselves: halo)
+  const int lw = lane > 0 ? lane - 1 : 0, le = lane < 63 ? lane + 1 : 63;
+
+  const AdjCoef<T> C(A);
+  const CapReader<T> cap1(A.cap, A.cnblk, col), cap2(A.cap2, A.cnblk, col);
+  const T *mu_src = (const T *)A.src;
+  AdjStage<T> S1, S2;
+  T mu1[9], mu2[9], mun[9];
+  T hn, jxn, jyn, kn = C.kap0;   // next input row of the step-t stage
+  T hm, jxm, jym, km = C.kap0;   // next input row of the step-(t-1) stage
+  hm = jxm = jym = 0;
+#pragma unroll
+  for (int l = 0; l < 9; ++l) mu1[l] = mu2[l] = 0;
+
+  // iteration k: step-t input row y0-5+k, step-t output row y0-7+k (k >= 4),
+  // step-(t-1) input row y0-8+k (k >= 6), step-(t-1) output row y0-10+k (k >= 10)
+  const int K = (yend - y0) + 10;
+  int r1 = wrap(y0 - 5, ny);
+  int r2 = wrap(y0 - 2, ny);
+  auto load1 = [&](int row) {
+    const size_t o = (size_t)row * ldx + col;
+#pragma unroll
+    for (int l = 0; l < 9; ++l) mun[l] = mu_src[(size_t)l * plane + o];
+    cap1.read(row, hn, jxn, jyn);
+    if constexpr (KF) kn = ((const T *)A.kfield)[o];
+  };
+  auto load2 = [&](int row) {
+    cap2.read(row, hm, jxm, jym);
+    if constexpr (KF) km = ((const T *)A.kfield)[(size_t)row * ldx + col];
+  };
+  load1(r1);
+
+  for (int k = 0; k < K; ++k) {
+    T mu0[9];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) mu0[l] = mun[l];
+    const T h = hn, jx = jxn, jy = jyn, kap = kn;
+    const T h_2 = hm, jx_2 = jxm, jy_2 = jym, kap_2 = km;
+    const int r1n = (r1 + 1 == ny) ? 0 : r1 + 1;
+    if (k + 1 < K) load1(r1n);
+    if (k + 1 >= 6 && k + 1 < K) {
+      load2(r2);
+      r2 = (r2 + 1 == ny) ? 0 : r2 + 1;
+    }
+
+    S1.push(mu0, h, jx, jy, kap, k >= 2, C);
+    if (k >= 4) {
+      T lam[9];
+      double gt;
+      S1.out(mu2, lam, gt, C);
+      const int s = k % 5;
+#pragma unroll
+      for (int l = 0; l < 9; ++l) ring[s][l][lane] = lam[l];
+      gring[k & 3][lane] = gt;
+    }
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      mu2[l] = mu1[l];
+      mu1[l] = mu0[l];
+    }
+    r1 = r1n;
+
+    if (k >= 6) {
+      __syncthreads();
+      // step-(t-1) input row y' = y0-8+k: lambda^t rows y'-1 .. y'+1 were
+      // written at iterations k-2 .. k
+      T m[9];
+#pragma unroll
+      for (int l = 0; l < 9; ++l)
+        m[l] = ring[(k - 1 + kCy[l]) % 5][l][kCx[l] == 0 ? lane : (kCx[l] > 0 ? le : lw)];
+      S2.push(m, h_2, jx_2, jy_2, kap_2, k >= 8, C);
+      if (k >= 10) {
+        // output row y = y' - 2; its mu from lambda^t rows y-1 .. y+1
+        const int y = y0 + (k - 10);
+        T mo[9];
+#pragma unroll
+        for (int l = 0; l < 9; ++l)
+          mo[l] = ring[(k - 3 + kCy[l]) % 5][l][kCx[l] == 0 ? lane : (kCx[l] > 0 ? le : lw)];
+        T lam[9];
+        double gt;
+        S2.out(mo, lam, gt, C);
+        if (out) {
+          store_pushed(A, y, col, colW, colE, lam);
+          double *gk = A.gk + (size_t)y * ldx + col;
+          double gsum = *gk;
+          gsum += gring[(k + 1) & 3][lane];  // the step-t term of row y, from iteration k-3
+          gsum += gt;
+          *gk = gsum;
+        }
+      }
+    }
   }
 }
 
@@ -338,15 +483,37 @@ __global__ void adj_finish_kernel(AdjArgs A, const double *h0, const double *the
 }
 
 template <typename T>
-static hipError_t adj_step_t(const AdjArgs &B, bool kf, hipStream_t s) {
+static hipError_t adj_step_t(const AdjArgs &B, bool kf, int ns, hipStream_t s) {
   const dim3 grid(8 * B.per_xcd), block(64);
-  if (kf) adj_step_kernel<T, true><<<grid, block, 0, s>>>(B);
-  else adj_step_kernel<T, false><<<grid, block, 0, s>>>(B);
+  if (ns == 2) {
+    if (kf) adj_step2_kernel<T, true><<<grid, block, 0, s>>>(B);
+    else adj_step2_kernel<T, false><<<grid, block, 0, s>>>(B);
+  } else {
+    if (kf) adj_step_kernel<T, true><<<grid, block, 0, s>>>(B);
+    else adj_step_kernel<T, false><<<grid, block, 0, s>>>(B);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_adj_step(int prec, const AdjArgs &B, bool kf, hipStream_t s) {
-  return prec == kF64 ? adj_step_t<double>(B, kf, s) : adj_step_t<float>(B, kf, s);
+hipError_t launch_adj_step(int prec, const AdjArgs &B, bool kf, int ns, hipStream_t s) {
+  return prec == kF64 ? adj_step_t<double>(B, kf, ns, s) : adj_step_t<float>(B, kf, ns, s);
+}
+
+template <typename T>
+static int adj_occupancy_t(bool kf, int ns) {
+  int n = 0;
+  hipError_t e;
+  if (ns == 2)
+    e = kf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_step2_kernel<T, true>, 64, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_step2_kernel<T, false>, 64, 0);
+  else
+    e = kf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_step_kernel<T, true>, 64, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_step_kernel<T, false>, 64, 0);
+  return e == hipSuccess ? n : 0;
+}
+
+int adj_blocks_per_cu(int prec, bool kf, int ns) {
+  return prec == kF64 ? adj_occupancy_t<double>(kf, ns) : adj_occupancy_t<float>(kf, ns);
 }
 
 hipError_t launch_adj_seed(int prec, const AdjArgs &B, const double *grad_h, hipStream_t s) {
@@ -369,7 +536,8 @@ hipError_t launch_adj_finish(int prec, const AdjArgs &B, const double *h0, const
 static size_t adj_buf_bytes(const tflbm_sim *s) { return 9 * (size_t)s->plane * work_bytes(s->p.prec); }
 static size_t round4k(size_t v) { return (v + 4095) / 4096 * 4096; }
 
-static AdjArgs make_adj_args(const tflbm_sim *s, void *d_adj) {
+// AdjArgs of the current adjoint buffers, shaped for `ns` steps per pass.
+static AdjArgs make_adj_args(const tflbm_sim *s, void *d_adj, int ns = 1) {
   AdjArgs B;
   std::memset(&B, 0, sizeof(B));
   char *base = (char *)d_adj;
@@ -383,10 +551,10 @@ static AdjArgs make_adj_args(const tflbm_sim *s, void *d_adj) {
   B.ldx = s->ldx;
   B.cnblk = s->nblk;
   B.plane = s->plane;
-  B.nstrips = s->adj_nstrips;
-  B.H = s->adj_rows;
-  B.ntiles = s->adj_ntiles;
-  B.per_xcd = s->adj_per_xcd;
+  B.nstrips = ns == 2 ? s->adj2_nstrips : s->adj_nstrips;
+  B.H = ns == 2 ? s->adj2_rows : s->adj_rows;
+  B.ntiles = ns == 2 ? s->adj2_ntiles : s->adj_ntiles;
+  B.per_xcd = ns == 2 ? s->adj2_per_xcd : s->adj_per_xcd;
   B.n_exp = s->p.n_exp;
   B.m_exp = s->p.m_exp;
   B.omega = 1.0 / s->p.tau;
@@ -429,9 +597,29 @@ int tflbm_adj_step(tflbm_sim *sim, void *d_adj, const void *d_capture_t, tflbm_s
   if (!sim->adj_seeded) return TFLBM_ESTATE;
   AdjArgs B = make_adj_args(sim, d_adj);
   B.cap = (const char *)d_capture_t;
-  const int rc = hip_status(sim, launch_adj_step(sim->p.prec, B, sim->kfield, (hipStream_t)stream));
+  const int rc = hip_status(sim, launch_adj_step(sim->p.prec, B, sim->kfield, 1, (hipStream_t)stream));
   if (rc) return rc;
   sim->adj_cur ^= 1;
+  return TFLBM_OK;
+}
+
+int tflbm_adj_steps(tflbm_sim *sim, void *d_adj, const void *d_capture, int64_t nsteps, tflbm_stream_t stream) {
+  if (!sim || !d_adj || nsteps < 0 || (nsteps > 0 && !d_capture)) return TFLBM_EINVAL;
+  if (!sim->adj_seeded) return TFLBM_ESTATE;
+  const size_t cb = (size_t)sim->p.ny * sim->nblk * capture_record_bytes(sim->p.prec);
+  const char *cap = (const char *)d_capture;
+  int64_t t = nsteps - 1;
+  while (t >= 0) {
+    const bool fuse = sim->adj_fuse == 2 || (sim->adj_fuse == 0 && sim->adj_fuse_fits);
+    const int ns = (t >= 1 && fuse) ? 2 : 1;
+    AdjArgs B = make_adj_args(sim, d_adj, ns);
+    B.cap = cap + (size_t)t * cb;
+    B.cap2 = ns == 2 ? cap + (size_t)(t - 1) * cb : nullptr;
+    const int rc = hip_status(sim, launch_adj_step(sim->p.prec, B, sim->kfield, ns, (hipStream_t)stream));
+    if (rc) return rc;
+    sim->adj_cur ^= 1;
+    t -= ns;
+  }
   return TFLBM_OK;
 }
 

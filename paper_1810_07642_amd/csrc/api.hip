@@ -59,9 +59,26 @@ void plan_launches(tflbm_sim *s) {
   s->rows2 = choose_rows(ny, s->nstrips, occ2 * cus, kMinRows, "TFLBM_ROWS2");
   s->ntiles2 = s->nstrips * ((ny + s->rows2 - 1) / s->rows2);
   s->per_xcd2 = (s->ntiles2 + 7) / 8;
-  s->adj_rows = choose_rows(ny, s->adj_nstrips, 2 * cus * 4, kMinRows, "TFLBM_ADJ_ROWS");
+  // Reverse steps: at most two resident wavefronts per SIMD are planned for
+  // (eight per CU).  At 4096^2 FP32 the one-step kernel, which fits three,
+  // ran 9% faster with chunks sized for two than for three.
+  int aocc1 = adj_blocks_per_cu(s->p.prec, s->kfield, 1);
+  int aocc2 = adj_blocks_per_cu(s->p.prec, s->kfield, 2);
+  aocc1 = aocc1 <= 0 || aocc1 > 8 ? 8 : aocc1;
+  aocc2 = aocc2 <= 0 || aocc2 > 8 ? 8 : aocc2;
+  s->adj_rows = choose_rows(ny, s->adj_nstrips, aocc1 * cus, kMinRows, "TFLBM_ADJ_ROWS");
   s->adj_ntiles = s->adj_nstrips * ((ny + s->adj_rows - 1) / s->adj_rows);
   s->adj_per_xcd = (s->adj_ntiles + 7) / 8;
+  s->adj2_rows = choose_rows(ny, s->adj2_nstrips, aocc2 * cus, kMinRows, "TFLBM_ADJ_ROWS2");
+  s->adj2_ntiles = s->adj2_nstrips * ((ny + s->adj2_rows - 1) / s->adj2_rows);
+  s->adj2_per_xcd = (s->adj2_ntiles + 7) / 8;
+  // Two reverse steps per pass pay off once the lattice fills the GPU: with
+  // fewer tiles of the shortest chunk than resident slots, a tile's time is
+  // its chain of rows, which the fused pass makes longer (ten halo rows, two
+  // stages per row) than two single passes (four halo rows each).  Measured
+  // at FP32: single steps win at 512^2 (11.2 vs 11.9 us per step), the fused
+  // pass from 768^2 on (14.8 vs 15.5; 4096^2: 281 vs 477).
+  s->adj_fuse_fits = (int64_t)s->adj2_nstrips * ((ny + kMinRows - 1) / kMinRows) > (int64_t)aocc2 * cus;
 }
 
 StepArgs make_step_args(const tflbm_sim *s, int ns) {
@@ -186,8 +203,9 @@ int tflbm_create(const tflbm_params *p, tflbm_sim **out) {
   s->kappa0 = (1.0 - std::cos(p->theta0)) * s->kconst;
   s->nstrips = s->nblk;  // one marching strip per record column
   if (const char *e = std::getenv("TFLBM_FUSE")) s->fuse = std::atoi(e) == 1 ? 1 : 2;
-  const int aw = adj_columns_per_strip();
-  s->adj_nstrips = (p->nx + aw - 1) / aw;
+  if (const char *e = std::getenv("TFLBM_ADJ_FUSE")) s->adj_fuse = std::atoi(e) == 1 ? 1 : 2;  // default 0: by lattice size
+  s->adj_nstrips = (p->nx + adj_columns_per_strip(1) - 1) / adj_columns_per_strip(1);
+  s->adj2_nstrips = (p->nx + adj_columns_per_strip(2) - 1) / adj_columns_per_strip(2);
   *out = s;
   return TFLBM_OK;
 }

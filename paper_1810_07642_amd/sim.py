@@ -185,6 +185,14 @@ class Sim:
         self._chk(self.lib.tflbm_adj_step(self.h, _addr(adj), _addr(capture_t), self.stream), "tflbm_adj_step")
         return self
 
+    def adj_steps(self, adj, captures, nsteps):
+        """Reverse pass over `nsteps` captured steps (two per pass over the lattice)."""
+        if captures.numel() < nsteps * self.capture_bytes():
+            raise ValueError("captures hold fewer than nsteps steps")
+        self._chk(self.lib.tflbm_adj_steps(self.h, _addr(adj), _addr(captures), int(nsteps), self.stream),
+                  "tflbm_adj_steps")
+        return self
+
     def adj_finish(self, adj, want_h0=True, want_theta=True):
         gh0 = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device) if want_h0 else None
         gth = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device) if want_theta else None

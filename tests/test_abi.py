@@ -114,6 +114,9 @@ def test_call_order_and_null_pointers(lib):
     assert lib.tflbm_mass(h, ctypes.byref(m), None) == _lib.TFLBM_ESTATE
     assert lib.tflbm_check(h, None) == _lib.TFLBM_ESTATE
     assert lib.tflbm_adj_step(h, ctypes.c_void_p(256), ctypes.c_void_p(256), None) == _lib.TFLBM_ESTATE
+    assert lib.tflbm_adj_steps(h, ctypes.c_void_p(256), ctypes.c_void_p(256), 4, None) == _lib.TFLBM_ESTATE
+    assert lib.tflbm_adj_steps(h, ctypes.c_void_p(256), ctypes.c_void_p(256), -1, None) == _lib.TFLBM_EINVAL
+    assert lib.tflbm_adj_steps(h, ctypes.c_void_p(256), None, 2, None) == _lib.TFLBM_EINVAL
     assert lib.tflbm_step_count(h) == 0
     assert lib.tflbm_step_count(None) == -1
     lib.tflbm_destroy(h)

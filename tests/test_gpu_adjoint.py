@@ -167,3 +167,58 @@ def test_adjoint_full_inverse_design_config():
     e_th = rel_l2(grads["fp32"][1], gth)
     print(f"FD pixels checked {checked}/64; FP32-forward gradient vs FP64: rel L2 h0 {e_h0:.2e}, theta {e_th:.2e}")
     assert e_h0 < 1e-2 and e_th < 1e-2
+
+
+def _reverse_pass(prec, h0, th, p, nsteps, grad_h, fused, field):
+    """(dL/dh0, dL/dtheta) of nsteps captured steps, the reverse pass either
+    through tflbm_adj_steps (two steps per pass) or one tflbm_adj_step per step."""
+    from paper_1810_07642_amd import Sim
+    ny, nx = h0.shape
+    kw = dict(p)
+    if not field:
+        kw["theta0"] = float(th[0, 0])
+    sim = Sim(nx, ny, prec, **kw).init(h0, th if field else None)
+    cb = sim.capture_bytes()
+    cap = torch.empty(nsteps * cb, dtype=torch.uint8, device="cuda")
+    adj = torch.empty(sim.adj_bytes(), dtype=torch.uint8, device="cuda")
+    sim.step_capture(nsteps, cap)
+    sim.adj_seed(adj, grad_h)
+    if fused:
+        sim.adj_steps(adj, cap, nsteps)
+    else:
+        for t in reversed(range(nsteps)):
+            sim.adj_step(adj, cap[t * cb:(t + 1) * cb])
+    g_h0, g_th = sim.adj_finish(adj)
+    torch.cuda.synchronize()
+    return g_h0.cpu(), g_th.cpu()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+@pytest.mark.parametrize("shape,rows2,field,nsteps", [
+    ((150, 173), "7", True, 7),      # four strips (the last 11 columns), 22 row chunks, the last of 3 rows
+    ((45, 70), None, False, 6),      # uniform kappa, an even number of steps
+    ((3, 2), None, True, 5),         # every row and column wraps onto the others
+])
+def test_two_steps_per_pass_equal_single_steps_bitwise(prec, shape, rows2, field, nsteps, monkeypatch):
+    """The two-step reverse pass hands the adjoint of step t to step t-1 on
+    chip instead of through memory; both stages round exactly as the single
+    step does, so the gradients must agree bit for bit (odd nsteps also runs
+    one single step at the end)."""
+    ny, nx = shape
+    banner(f"adjoint two steps per pass vs single steps: {prec} {ny}x{nx}, {nsteps} steps, rows {rows2}, field {field}")
+    monkeypatch.setenv("TFLBM_ADJ_FUSE", "2")  # two steps per pass also on lattices this small
+    if rows2 is not None:
+        monkeypatch.setenv("TFLBM_ADJ_ROWS2", rows2)
+    h0, th = random_case(ny, nx, 77)
+    p = dict(tau=0.8, gamma=0.02, g=1e-3, hstar=0.15, delta=0.8, ax=2e-5, ay=-1e-5)
+    if prec != "fp64":
+        p["href"] = 0.45
+    g = torch.Generator().manual_seed(78)
+    grad_h = torch.randn((ny, nx), generator=g, dtype=torch.float64)
+    a = _reverse_pass(prec, h0, th, p, nsteps, grad_h, True, field)
+    b = _reverse_pass(prec, h0, th, p, nsteps, grad_h, False, field)
+    for x, y, name in ((a[0], b[0], "dL/dh0"), (a[1], b[1], "dL/dtheta")):
+        assert torch.isfinite(y).all(), name
+        nd = int((x != y).sum())
+        print(f"{name}: {nd} differing sites, max |diff| {float((x - y).abs().max()):.3e}")
+        assert nd == 0, name
