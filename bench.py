@@ -244,6 +244,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline FP32 number only")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run this many FP32 steps and a 1 GiB device copy (for rocprofv3), then exit")
+    ap.add_argument("--profile-adjoint", type=int, default=0,
+                    help="run the reverse pass over this many captured FP32 steps and a 1 GiB device copy "
+                         "(for rocprofv3), then exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -260,16 +263,25 @@ def main():
     # FP32 storage as deviations from the rest equilibrium at the mean film height
     href = 0.1
 
-    if args.profile_steps:
+    if args.profile_steps or args.profile_adjoint:
         sim = Sim(n, n, "fp32", href=href, **p).init(h0, th)
-        sim.step(args.profile_steps)
+        if args.profile_adjoint:
+            k = args.profile_adjoint
+            cap = torch.empty(k * sim.capture_bytes(), dtype=torch.uint8, device="cuda")
+            adj = torch.empty(sim.adj_bytes(), dtype=torch.uint8, device="cuda")
+            sim.step_capture(k, cap)
+            sim.adj_seed(adj, torch.zeros(n, n, dtype=torch.float64))
+            sim.adj_steps(adj, cap, k)
+        else:
+            sim.step(args.profile_steps)
         torch.cuda.synchronize()
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
         src.fill_(1.0)
         dst.copy_(src)
         torch.cuda.synchronize()
-        log(f"profile run: {args.profile_steps} fp32 steps at {n}^2 and a 1 GiB copy")
+        what = f"reverse pass over {args.profile_adjoint} captured" if args.profile_adjoint else f"{args.profile_steps}"
+        log(f"profile run: {what} fp32 steps at {n}^2 and a 1 GiB copy")
         return
 
     ms32, h32, m32 = run_form("fp32", p, h0, th, args.steps, args.warmup, href=href)

@@ -356,8 +356,10 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
   AdjStage<T> S1, S2;
   T mu1[9], mu2[9], mun[9];
   T hn, jxn, jyn, kn = C.kap0;   // next input row of the step-t stage
-  T hm, jxm, jym, km = C.kap0;   // next input row of the step-(t-1) stage
-  hm = jxm = jym = 0;
+  T hm = 0, jxm = 0, jym = 0;    // next input row of the step-(t-1) stage
+  // kappa of the step-t input rows of the last three iterations: the
+  // step-(t-1) stage takes each row three iterations later
+  T kd1 = C.kap0, kd2 = C.kap0, kd3 = C.kap0;
 #pragma unroll
   for (int l = 0; l < 9; ++l) mu1[l] = mu2[l] = 0;
 
@@ -373,10 +375,7 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
     cap1.read(row, hn, jxn, jyn);
     if constexpr (KF) kn = ((const T *)A.kfield)[o];
   };
-  auto load2 = [&](int row) {
-    cap2.read(row, hm, jxm, jym);
-    if constexpr (KF) km = ((const T *)A.kfield)[(size_t)row * ldx + col];
-  };
+  auto load2 = [&](int row) { cap2.read(row, hm, jxm, jym); };
   load1(r1);
 
   for (int k = 0; k < K; ++k) {
@@ -384,7 +383,10 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
 #pragma unroll
     for (int l = 0; l < 9; ++l) mu0[l] = mun[l];
     const T h = hn, jx = jxn, jy = jyn, kap = kn;
-    const T h_2 = hm, jx_2 = jxm, jy_2 = jym, kap_2 = km;
+    const T h_2 = hm, jx_2 = jxm, jy_2 = jym, kap_2 = kd3;
+    kd3 = kd2;
+    kd2 = kd1;
+    kd1 = kap;
     const int r1n = (r1 + 1 == ny) ? 0 : r1 + 1;
     if (k + 1 < K) load1(r1n);
     if (k + 1 >= 6 && k + 1 < K) {
