@@ -113,7 +113,13 @@ int tflbm_check_params(const tflbm_params *p);
 
 /* Creates a handle for the lattice and parameters in *p (copied).  Performs
  * the TFLBM_EINVAL checks of tflbm_check_params; a TFLBM_EUNSTABLE warning
- * does not prevent creation.  *out receives the handle or NULL. */
+ * does not prevent creation.  *out receives the handle or NULL.
+ * Launch-shape overrides, read from the environment here (fusion) and at
+ * tflbm_init (row chunks), for measurement only; results do not depend on
+ * them: TFLBM_FUSE=1 (one forward step per pass), TFLBM_ADJ_FUSE=1 or 2 (one
+ * or two reverse steps per pass in tflbm_adj_steps; default: two when the
+ * lattice fills the GPU), TFLBM_ROWS, TFLBM_ROWS2, TFLBM_ADJ_ROWS,
+ * TFLBM_ADJ_ROWS2 (rows per chunk of the one- and two-step kernels). */
 int tflbm_create(const tflbm_params *p, tflbm_sim **out);
 
 /* Releases the handle (host memory only; no device memory is owned). */

@@ -37,10 +37,15 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("fuse", ["auto", "2"])
 @pytest.mark.parametrize("case", range(len(CASES)))
-def test_fp64_adjoint_matches_oracle_gradient(case):
+def test_fp64_adjoint_matches_oracle_gradient(case, fuse, monkeypatch):
+    """fuse = "2": two reverse steps per pass also on these small lattices
+    (by default they run single steps)."""
     ny, nx, steps, K, p = CASES[case]
-    banner(f"fp64 adjoint case {case}: {ny}x{nx}, {steps} steps, K={K}")
+    banner(f"fp64 adjoint case {case}: {ny}x{nx}, {steps} steps, K={K}, reverse steps per pass: {fuse}")
+    if fuse != "auto":
+        monkeypatch.setenv("TFLBM_ADJ_FUSE", fuse)
     h0, th = random_case(ny, nx, 200 + case)
     g = torch.Generator().manual_seed(300 + case)
     grad_h = torch.randn((ny, nx), generator=g, dtype=torch.float64)
