@@ -608,7 +608,7 @@ int tflbm_adj_step(tflbm_sim *sim, void *d_adj, const void *d_capture_t, tflbm_s
 int tflbm_adj_steps(tflbm_sim *sim, void *d_adj, const void *d_capture, int64_t nsteps, tflbm_stream_t stream) {
   if (!sim || !d_adj || nsteps < 0 || (nsteps > 0 && !d_capture)) return TFLBM_EINVAL;
   if (!sim->adj_seeded) return TFLBM_ESTATE;
-  const size_t cb = (size_t)sim->p.ny * sim->nblk * capture_record_bytes(sim->p.prec);
+  const size_t cb = tflbm_capture_bytes(sim);
   const char *cap = (const char *)d_capture;
   int64_t t = nsteps - 1;
   while (t >= 0) {
