@@ -26,6 +26,10 @@ int main(void) {
     double m = 0.0, norms[8];
     EXPECT(tflbm_mass(s, &m, NULL) == TFLBM_ESTATE);
     EXPECT(tflbm_term_norms(s, norms, NULL) == TFLBM_ESTATE);
+    char fake[256];
+    EXPECT(tflbm_adj_step(s, fake, fake, NULL) == TFLBM_ESTATE);
+    EXPECT(tflbm_adj_steps(s, fake, fake, 3, NULL) == TFLBM_ESTATE);
+    EXPECT(tflbm_adj_steps(s, fake, fake, -1, NULL) == TFLBM_EINVAL);
     EXPECT(tflbm_step_count(s) == 0);
     EXPECT(strlen(tflbm_strerror(TFLBM_ESTATE)) > 0 && strlen(tflbm_last_error(s)) == 0);
     tflbm_destroy(s);
