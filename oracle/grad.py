@@ -56,3 +56,18 @@ def misfit_grad(h0, theta, target, p, nsteps, K=64):
         loss = 0.5 * float((grad_h ** 2).sum())
     g_h0, g_theta = vjp(h0, theta, grad_h, p, nsteps, K)
     return loss, g_h0, g_theta
+
+
+def jvp(h0, theta, v_h0, v_theta, p, nsteps):
+    """Forward-mode derivative of the final height, J (v_h0, v_theta), with
+    torch.func.jvp through the same forward step (no checkpointing): a
+    differentiation independent of the reverse mode above, for dot-product
+    tests <w, J v> = <J^T w, v>."""
+    def fn(a, b):
+        f = lbm.run(lbm.init(a, p), lbm.kappa(b, p), p, nsteps)
+        h, _, _ = lbm.moments(f)
+        return h
+    args = (h0.detach().to(lbm.DTYPE), theta.detach().to(lbm.DTYPE))
+    tangents = (v_h0.detach().to(lbm.DTYPE), v_theta.detach().to(lbm.DTYPE))
+    _, jv = torch.func.jvp(fn, args, tangents)
+    return jv.detach()

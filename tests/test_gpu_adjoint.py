@@ -57,6 +57,26 @@ def test_fp64_adjoint_matches_oracle_gradient(case, fuse, monkeypatch):
     assert float((gh0 - gh0_o).abs().max()) <= 1e-10 * float(gh0_o.abs().max())
 
 
+@pytest.mark.parametrize("fuse", ["1", "2"])
+def test_adjoint_dot_product_against_oracle_forward_mode(fuse, monkeypatch):
+    """<w, J v> from the oracle's forward-mode derivative (torch.func.jvp,
+    no reverse mode involved) against <J^T w, v> from the hand-written GPU
+    adjoint (FP64), one and two reverse steps per pass, 7 steps."""
+    ny, nx, steps = 37, 70, 7
+    banner(f"adjoint dot-product test {ny}x{nx}, {steps} steps, reverse steps per pass {fuse}")
+    monkeypatch.setenv("TFLBM_ADJ_FUSE", fuse)
+    p = dict(tau=0.8, gamma=0.02, g=-1e-3, hstar=0.15, delta=0.8, ax=2e-5, ay=-1e-5)
+    h0, th = random_case(ny, nx, 91)
+    g = torch.Generator().manual_seed(92)
+    vh, vt, w = (torch.randn((ny, nx), generator=g, dtype=torch.float64) for _ in range(3))
+    jv = ograd.jvp(h0, th, vh, vt, lbm.Params(**p), steps)
+    _, gh0, gth = gpu_grads(p, h0, th, w, steps, 4, "fp64")
+    lhs = float((w * jv).sum())
+    rhs = float((gh0 * vh).sum() + (gth * vt).sum())
+    print(f"<w, Jv> = {lhs:.15e}, <J^T w, v> = {rhs:.15e}, rel diff {abs(lhs - rhs) / abs(lhs):.2e}")
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
 def test_adjoint_inverse_design_64_copy():
     """The inverse-design case on a 64 x 64 copy: dewetting recipe, theta = pi/6,
     smooth target, L = 1/2 sum (h_N - target)^2, 256 steps checkpointed every 64;

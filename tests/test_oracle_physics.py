@@ -109,6 +109,25 @@ def test_sampled_windows_match_whole_grid():
         assert abs(float(uys[i] - uy[y, x])) <= 1e-12 * float(uy.abs().max())
 
 
+def test_gradient_oracle_forward_and_reverse_modes_agree():
+    """Dot-product test <w, J v> = <J^T w, v>: the reverse-mode gradient
+    oracle (autograd with recompute) against forward-mode differentiation of
+    the same step (torch.func.jvp), a differentiation that shares no
+    bookkeeping with it.  A dropped or transposed term in either shows as a
+    mismatch far above rounding."""
+    ny, nx, steps = 14, 18, 6
+    g = torch.Generator().manual_seed(11)
+    h0 = 0.3 + 0.3 * torch.rand((ny, nx), generator=g, dtype=F64)
+    th = 0.2 + 0.5 * torch.rand((ny, nx), generator=g, dtype=F64)
+    vh, vt, w = (torch.randn((ny, nx), generator=g, dtype=F64) for _ in range(3))
+    P = lbm.Params(tau=0.8, gamma=0.02, g=1e-3, hstar=0.15, delta=0.8, ax=2e-5, ay=-1e-5)
+    jv = ograd.jvp(h0, th, vh, vt, P, steps)
+    gh, gt = ograd.vjp(h0, th, w, P, steps, K=4)
+    lhs = float((w * jv).sum())
+    rhs = float((gh * vh).sum() + (gt * vt).sum())
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+
+
 def test_gradient_oracle_against_finite_differences():
     """Autograd gradient (with recompute every K steps) against central finite
     differences of the forward oracle at seeded pixels, for h0 and theta."""
