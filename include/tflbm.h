@@ -116,9 +116,10 @@ int tflbm_check_params(const tflbm_params *p);
  * does not prevent creation.  *out receives the handle or NULL.
  * Launch-shape overrides, read from the environment here (fusion) and at
  * tflbm_init (row chunks), for measurement only; results do not depend on
- * them: TFLBM_FUSE=1 (one forward step per pass), TFLBM_ADJ_FUSE=1 or 2 (one
- * or two reverse steps per pass in tflbm_adj_steps; default: two when the
- * lattice fills the GPU), TFLBM_ROWS, TFLBM_ROWS2, TFLBM_ADJ_ROWS,
+ * them: TFLBM_FUSE=1 or 2 (one or two forward steps per pass in tflbm_step
+ * and tflbm_step_capture), TFLBM_ADJ_FUSE=1 or 2 (the same for the reverse
+ * steps of tflbm_adj_steps; by default two where the lattice is large enough
+ * for it to pay), TFLBM_ROWS, TFLBM_ROWS2, TFLBM_ADJ_ROWS,
  * TFLBM_ADJ_ROWS2 (rows per chunk of the one- and two-step kernels). */
 int tflbm_create(const tflbm_params *p, tflbm_sim **out);
 

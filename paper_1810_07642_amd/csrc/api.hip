@@ -37,9 +37,15 @@ int choose_rows(int ny, int nstrips, int slots, int min_rows, const char *env_na
 
 // Shortest row chunk a tile marches.  On small lattices, where one round of
 // tiles cannot fill the GPU anyway, a tile's time is its chain of rows (chunk
-// plus halo rows) and short chunks win; below 4 rows the re-read halo rows
-// (4 for one step, 10 for two fused steps) dominate the traffic.
-constexpr int kMinRows = 4;
+// plus halo rows) and short chunks win.  Measured (FP32, microseconds per
+// step): the forward step and the one-step reverse pass are fastest with
+// one-row chunks wherever the plan picks them (forward 128^2: 5.4 against 9.0
+// with four-row chunks; reverse 256^2: 6.4 against 8.7); the two-step reverse
+// pass, with ten halo rows per chunk, needs at least four (512^2: 11.3 with
+// three rows, 15.1 with two).
+constexpr int kMinRowsStep = 1;
+constexpr int kMinRowsAdj = 1;
+constexpr int kMinRowsAdj2 = 4;
 
 // Launch shapes of the step kernels for the device current at the call.
 void plan_launches(tflbm_sim *s) {
@@ -53,12 +59,19 @@ void plan_launches(tflbm_sim *s) {
   int occ2 = step_blocks_per_cu(s->p.prec, s->kfield, 2);
   if (occ1 <= 0) occ1 = 8;
   if (occ2 <= 0) occ2 = 8;
-  s->rows = choose_rows(ny, s->nstrips, occ1 * cus, kMinRows, "TFLBM_ROWS");
+  s->rows = choose_rows(ny, s->nstrips, occ1 * cus, kMinRowsStep, "TFLBM_ROWS");
   s->ntiles = s->nstrips * ((ny + s->rows - 1) / s->rows);
   s->per_xcd = (s->ntiles + 7) / 8;
-  s->rows2 = choose_rows(ny, s->nstrips, occ2 * cus, kMinRows, "TFLBM_ROWS2");
+  s->rows2 = choose_rows(ny, s->nstrips, occ2 * cus, kMinRowsStep, "TFLBM_ROWS2");
   s->ntiles2 = s->nstrips * ((ny + s->rows2 - 1) / s->rows2);
   s->per_xcd2 = (s->ntiles2 + 7) / 8;
+  // Two fused steps per pass pay off once the one-step plan can no longer give
+  // every row a tile of its own in one round of resident wavefronts: below
+  // that a tile's time is its chain of rows, 5 for one step against 11 per
+  // two fused steps, each of those twice the work.  Measured per step at FP32:
+  // 128^2 5.4 vs 6.4 us, 256^2 6.0 vs 6.8, 512^2 9.2 vs 9.4; from 768^2 on
+  // the fused pass wins.
+  s->fuse_fits = (int64_t)s->nstrips * ny > (int64_t)occ1 * cus;
   // Reverse steps: at most two resident wavefronts per SIMD are planned for
   // (eight per CU).  At 4096^2 FP32 the one-step kernel, which fits three,
   // ran 9% faster with chunks sized for two than for three.
@@ -66,10 +79,10 @@ void plan_launches(tflbm_sim *s) {
   int aocc2 = adj_blocks_per_cu(s->p.prec, s->kfield, 2);
   aocc1 = aocc1 <= 0 || aocc1 > 8 ? 8 : aocc1;
   aocc2 = aocc2 <= 0 || aocc2 > 8 ? 8 : aocc2;
-  s->adj_rows = choose_rows(ny, s->adj_nstrips, aocc1 * cus, kMinRows, "TFLBM_ADJ_ROWS");
+  s->adj_rows = choose_rows(ny, s->adj_nstrips, aocc1 * cus, kMinRowsAdj, "TFLBM_ADJ_ROWS");
   s->adj_ntiles = s->adj_nstrips * ((ny + s->adj_rows - 1) / s->adj_rows);
   s->adj_per_xcd = (s->adj_ntiles + 7) / 8;
-  s->adj2_rows = choose_rows(ny, s->adj2_nstrips, aocc2 * cus, kMinRows, "TFLBM_ADJ_ROWS2");
+  s->adj2_rows = choose_rows(ny, s->adj2_nstrips, aocc2 * cus, kMinRowsAdj2, "TFLBM_ADJ_ROWS2");
   s->adj2_ntiles = s->adj2_nstrips * ((ny + s->adj2_rows - 1) / s->adj2_rows);
   s->adj2_per_xcd = (s->adj2_ntiles + 7) / 8;
   // Two reverse steps per pass pay off once the lattice fills the GPU: with
@@ -78,7 +91,7 @@ void plan_launches(tflbm_sim *s) {
   // stages per row) than two single passes (four halo rows each).  Measured
   // at FP32: single steps win at 512^2 (11.2 vs 11.9 us per step), the fused
   // pass from 768^2 on (14.8 vs 15.5; 4096^2: 281 vs 477).
-  s->adj_fuse_fits = (int64_t)s->adj2_nstrips * ((ny + kMinRows - 1) / kMinRows) > (int64_t)aocc2 * cus;
+  s->adj_fuse_fits = (int64_t)s->adj2_nstrips * ((ny + kMinRowsAdj2 - 1) / kMinRowsAdj2) > (int64_t)aocc2 * cus;
 }
 
 StepArgs make_step_args(const tflbm_sim *s, int ns) {
@@ -202,7 +215,7 @@ int tflbm_create(const tflbm_params *p, tflbm_sim **out) {
   s->kconst = (double)((p->n_exp - 1) * (p->m_exp - 1)) / ((double)(p->n_exp - p->m_exp) * p->hstar);
   s->kappa0 = (1.0 - std::cos(p->theta0)) * s->kconst;
   s->nstrips = s->nblk;  // one marching strip per record column
-  if (const char *e = std::getenv("TFLBM_FUSE")) s->fuse = std::atoi(e) == 1 ? 1 : 2;
+  if (const char *e = std::getenv("TFLBM_FUSE")) s->fuse = std::atoi(e) == 1 ? 1 : 2;  // default 0: by lattice size
   if (const char *e = std::getenv("TFLBM_ADJ_FUSE")) s->adj_fuse = std::atoi(e) == 1 ? 1 : 2;  // default 0: by lattice size
   s->adj_nstrips = (p->nx + adj_columns_per_strip(1) - 1) / adj_columns_per_strip(1);
   s->adj2_nstrips = (p->nx + adj_columns_per_strip(2) - 1) / adj_columns_per_strip(2);
@@ -249,7 +262,7 @@ static int run_steps(tflbm_sim *sim, int64_t nsteps, void *d_capture, tflbm_stre
   hipStream_t st = (hipStream_t)stream;
   const size_t cap_bytes = tflbm_capture_bytes(sim);
   int64_t i = 0;
-  if (sim->fuse == 2) {
+  if (sim->fuse == 2 || (sim->fuse == 0 && sim->fuse_fits)) {
     // two fused steps per pass while at least two remain (with capture: the
     // moments of step i and of step i + 1, one capture block apart)
     for (; i + 2 <= nsteps; i += 2) {

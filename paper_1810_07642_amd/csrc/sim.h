@@ -25,7 +25,8 @@ struct tflbm_sim {
   // launch shape of the forward step: one step per pass, and two fused steps
   int nstrips = 0, rows = 0, ntiles = 0, per_xcd = 0;
   int rows2 = 0, ntiles2 = 0, per_xcd2 = 0;
-  int fuse = 2;           // steps fused per pass when possible (1 or 2)
+  int fuse = 0;           // steps per pass: 1, 2 (when possible), 0 = 2 if fuse_fits
+  bool fuse_fits = false; // the lattice is too large for one round of one-row tiles
   // reverse pass
   int adj_cur = 0;        // 0: first adjoint buffer holds the current adjoint
   bool adj_seeded = false;
