@@ -7,6 +7,7 @@ include/tflbm.h); this package is its thin Python binding:
   TFLBMRun   -- torch.autograd.Function: gradient of the final height w.r.t. h0 and theta
   design     -- inverse design: Adam on theta(x, y) through TFLBMRun (fit_contact_angle)
   spreading  -- spreading-drop tracking: cap geometry, Tanner exponent, Cox-Voinov fit
+  sliding    -- sliding drop under a body force: steady capillary number
   inputs     -- seeded synthetic initial conditions and parameter sets
   build      -- compiles libtflbm.so
 """
