@@ -104,7 +104,8 @@ def run_form(prec, p, h0, th, steps, warmup, fuse=None, href=0.0):
 
 def adjoint_ratio(prec="fp32", n=512, steps=4096, K=64):
     """Backward (recompute + adjoint) over forward (with checkpoints) wall time
-    of the inverse-design case."""
+    of the inverse-design case; with K = 0 the forward writes every step's
+    capture and the backward is the reverse pass alone."""
     import torch
     from paper_1810_07642_amd import TFLBMRun, inputs
     p, h0, th, target = inputs.inverse_design(n=n)
@@ -356,6 +357,8 @@ def main():
         del h16, h64ref
         torch.cuda.empty_cache()
         extras["adjoint"] = adjoint_ratio()
+        # the same case with every step's capture kept (K = 0: no checkpoints, no recompute)
+        extras["adjoint_all_captures_kept"] = adjoint_ratio(K=0)
         extras["reverse_sweep_at_headline_size"] = reverse_sweep_at(n)
         line["extras"] = extras
         log(f"fp64 {mlups64:.0f} MLUPS, fp16s {mlups16:.0f} MLUPS, adjoint/forward {extras['adjoint']['ratio']:.2f}")

@@ -7,7 +7,9 @@ target height field: it minimises
     L(theta) = 1/2 sum_x (h_N(x; theta) - h_target(x))^2
 
 with Adam, the gradient dL/dtheta coming from TFLBMRun (hand-written adjoint
-step, checkpoints every K steps, recompute with captured moments).  theta is
+step; by default every step's captured moments are kept when they take at
+most a quarter of the free device memory, else checkpoints every 64 steps and
+a recompute).  theta is
 kept inside (0, theta_max) by the parametrisation theta = theta_max sigmoid(z),
 and z is what Adam moves.
 
@@ -30,13 +32,25 @@ class FitResult:
 
 
 
-def fit_contact_angle(h0, target, params, nsteps, theta_init=math.pi / 6, iters=60, lr=0.1, K=64,
+def checkpoint_interval(nx, ny, nsteps, prec="fp32", fraction=0.25):
+    """K for TFLBMRun: 0 (keep every step's capture, no recompute) when the
+    nsteps captures take at most `fraction` of the free memory of the current
+    GPU, else 64."""
+    from .sim import capture_bytes_for
+    free, _ = torch.cuda.mem_get_info()
+    return 0 if nsteps * capture_bytes_for(nx, ny, prec) <= fraction * free else 64
+
+
+def fit_contact_angle(h0, target, params, nsteps, theta_init=math.pi / 6, iters=60, lr=0.1, K=None,
                       prec="fp32", theta_max=math.pi / 2, callback=None):
     """Adam on z, theta = theta_max sigmoid(z).  h0, target: [ny, nx] tensors
     (moved to the current GPU in float64); theta_init: a scalar or a field.
+    K: TFLBMRun's checkpoint interval (None: checkpoint_interval).
     callback(it, loss, theta) is called every iteration if given."""
     dev = torch.device("cuda", torch.cuda.current_device())
     h0 = torch.as_tensor(h0, dtype=torch.float64).to(dev)
+    if K is None:
+        K = checkpoint_interval(h0.shape[1], h0.shape[0], nsteps, prec)
     tgt = torch.as_tensor(target, dtype=torch.float64).to(dev)
     th0 = torch.as_tensor(theta_init, dtype=torch.float64)
     if th0.dim() == 0:

@@ -54,6 +54,19 @@ def make_params(nx, ny, prec="fp64", **kw):
     return p
 
 
+def capture_bytes_for(nx, ny, prec="fp64"):
+    """Bytes of one step's capture (tflbm_capture_bytes) for a lattice, from a
+    handle that binds no workspace."""
+    lib = _lib.load()
+    p = make_params(nx, ny, prec)
+    h = ctypes.c_void_p()
+    _lib.check(lib.tflbm_create(ctypes.byref(p), ctypes.byref(h)), "tflbm_create")
+    try:
+        return int(lib.tflbm_capture_bytes(h))
+    finally:
+        lib.tflbm_destroy(h)
+
+
 def check_params(nx, ny, prec="fp64", **kw):
     """TFLBM_OK, TFLBM_EINVAL or TFLBM_EUNSTABLE for a parameter set."""
     return _lib.load().tflbm_check_params(ctypes.byref(make_params(nx, ny, prec, **kw)))

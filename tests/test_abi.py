@@ -93,6 +93,8 @@ def test_workspace_and_state_sizes(lib, prec, per_site):
     # capture: records of the same B columns, three segments padded to whole lines
     assert lib.tflbm_capture_bytes(h) == 30 * nblk * (-(-3 * B * wb // 128) * 128)
     assert lib.tflbm_adj_bytes(h) >= 2 * 9 * wb * ldx * 30 + 8 * ldx * 30
+    from paper_1810_07642_amd.sim import capture_bytes_for
+    assert capture_bytes_for(100, 30, {0: "fp64", 1: "fp32", 2: "fp16s"}[prec]) == lib.tflbm_capture_bytes(h)
     lib.tflbm_destroy(h)
 
 
