@@ -41,3 +41,15 @@ def test_inverse_design_recovers_stripe_pattern():
     assert corr > 0.99
     assert abs(float(th[lo].mean()) - math.pi / 9) < 0.04
     assert abs(float(th[hi].mean()) - math.pi / 4) < 0.04
+
+
+def test_checkpoint_interval_keeps_captures_when_they_fit():
+    """K = 0 (every capture kept) when nsteps captures take at most the given
+    fraction of free device memory, else checkpoints every 64 steps."""
+    from paper_1810_07642_amd.design import checkpoint_interval
+    from paper_1810_07642_amd.sim import capture_bytes_for
+    free, _ = torch.cuda.mem_get_info()
+    cb = capture_bytes_for(512, 512, "fp32")
+    fits = int(0.25 * free // cb)
+    assert checkpoint_interval(512, 512, fits, "fp32") == 0
+    assert checkpoint_interval(512, 512, 2 * fits + 100, "fp32") == 64
