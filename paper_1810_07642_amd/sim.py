@@ -24,6 +24,21 @@ def _addr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _buf(t, nbytes, device, name):
+    """Checks that a caller-supplied buffer is a contiguous tensor on the
+    handle's device holding at least nbytes (the library dereferences its
+    address on the GPU)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor")
+    if t.device != device:
+        raise ValueError(f"{name}: on {t.device}, the lattice is on {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: not contiguous")
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{name}: {t.numel() * t.element_size()} bytes, needs {nbytes}")
+    return t
+
+
 def _dev_f64(t, device, shape, name):
     if t is None:
         return None
@@ -78,6 +93,8 @@ class Sim:
     def __init__(self, nx, ny, prec="fp64", device=None, **params):
         self.lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         if self.device.type != "cuda":
             raise ValueError("Sim needs a GPU device")
         self.nx, self.ny = int(nx), int(ny)
@@ -164,12 +181,12 @@ class Sim:
     def state_save(self, out=None):
         if out is None:
             out = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        _buf(out, self.state_bytes(), self.device, "checkpoint buffer")
         self._chk(self.lib.tflbm_state_save(self.h, _addr(out), self.stream), "tflbm_state_save")
         return out
 
     def state_load(self, buf, step):
-        if buf.numel() * buf.element_size() < self.state_bytes():
-            raise ValueError("checkpoint buffer too small")
+        _buf(buf, self.state_bytes(), self.device, "checkpoint buffer")
         self._chk(self.lib.tflbm_state_load(self.h, _addr(buf), int(step), self.stream), "tflbm_state_load")
         return self
 
@@ -178,9 +195,7 @@ class Sim:
         return int(self.lib.tflbm_capture_bytes(self.h))
 
     def step_capture(self, nsteps, capture):
-        need = nsteps * self.capture_bytes()
-        if capture.numel() * capture.element_size() < need:
-            raise ValueError("capture buffer too small")
+        _buf(capture, int(nsteps) * self.capture_bytes(), self.device, "capture buffer")
         self._chk(self.lib.tflbm_step_capture(self.h, int(nsteps), _addr(capture), self.stream),
                   "tflbm_step_capture")
         return self
@@ -189,24 +204,29 @@ class Sim:
         return int(self.lib.tflbm_adj_bytes(self.h))
 
     def adj_seed(self, adj, grad_h):
+        _buf(adj, self.adj_bytes(), self.device, "adjoint workspace")
         g = _dev_f64(grad_h, self.device, (self.ny, self.nx), "grad_h")
         self._chk(self.lib.tflbm_adj_seed(self.h, _addr(adj), _addr(g), self.stream), "tflbm_adj_seed")
         self._seed_keepalive = g
         return self
 
     def adj_step(self, adj, capture_t):
+        _buf(adj, self.adj_bytes(), self.device, "adjoint workspace")
+        _buf(capture_t, self.capture_bytes(), self.device, "capture")
         self._chk(self.lib.tflbm_adj_step(self.h, _addr(adj), _addr(capture_t), self.stream), "tflbm_adj_step")
         return self
 
     def adj_steps(self, adj, captures, nsteps):
-        """Reverse pass over `nsteps` captured steps (two per pass over the lattice)."""
-        if captures.numel() < nsteps * self.capture_bytes():
-            raise ValueError("captures hold fewer than nsteps steps")
+        """Reverse pass over `nsteps` captured steps (tflbm_adj_steps: two per
+        pass over the lattice where that pays)."""
+        _buf(adj, self.adj_bytes(), self.device, "adjoint workspace")
+        _buf(captures, int(nsteps) * self.capture_bytes(), self.device, "captures")
         self._chk(self.lib.tflbm_adj_steps(self.h, _addr(adj), _addr(captures), int(nsteps), self.stream),
                   "tflbm_adj_steps")
         return self
 
     def adj_finish(self, adj, want_h0=True, want_theta=True):
+        _buf(adj, self.adj_bytes(), self.device, "adjoint workspace")
         gh0 = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device) if want_h0 else None
         gth = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device) if want_theta else None
         self._chk(self.lib.tflbm_adj_finish(self.h, _addr(adj), _addr(self.h0), _addr(self.theta),

@@ -281,3 +281,29 @@ def test_keeping_every_capture_equals_checkpoint_and_recompute(prec):
     for a, b in zip(res[0], res[1]):
         assert torch.isfinite(a).all()
         assert torch.equal(a, b)
+
+
+def test_binding_rejects_buffers_it_cannot_hand_to_the_library():
+    """Host tensors and short buffers are refused before any HIP call."""
+    from paper_1810_07642_amd import Sim
+    h0, th = random_case(12, 20, 7)
+    sim = Sim(20, 12, "fp32", device="cuda", tau=0.9, gamma=0.01, hstar=0.1).init(h0, th)
+    assert sim.device.index is not None
+    adj = torch.empty(sim.adj_bytes(), dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        sim.adj_seed(torch.empty(sim.adj_bytes(), dtype=torch.uint8), torch.zeros(12, 20))
+    with pytest.raises(ValueError):
+        sim.adj_seed(adj[:-1], torch.zeros(12, 20))
+    sim.adj_seed(adj, torch.zeros(12, 20))
+    cap = torch.empty(3 * sim.capture_bytes(), dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        sim.step_capture(4, cap)
+    with pytest.raises(ValueError):
+        sim.adj_steps(adj, cap, 4)
+    with pytest.raises(ValueError):
+        sim.state_load(torch.empty(sim.state_bytes(), dtype=torch.uint8), 0)
+    sim.step_capture(3, cap)
+    sim.adj_steps(adj, cap, 3)
+    g_h0, g_th = sim.adj_finish(adj)
+    torch.cuda.synchronize()
+    assert torch.isfinite(g_h0).all() and torch.isfinite(g_th).all()
