@@ -144,6 +144,11 @@ class Sim:
         if out is None:
             out = tuple(torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device) for _ in range(3))
         h, ux, uy = out
+        for t, name in ((h, "h"), (ux, "ux"), (uy, "uy")):
+            if t is not None:
+                _buf(t, 8 * self.nx * self.ny, self.device, name)
+                if t.dtype != torch.float64:
+                    raise ValueError(f"{name}: expected float64")
         self._chk(self.lib.tflbm_read(self.h, _addr(h), _addr(ux), _addr(uy), self.stream), "tflbm_read")
         return h, ux, uy
 
