@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--profile-adjoint", type=int, default=0,
                     help="run the reverse pass over this many captured FP32 steps and a 1 GiB device copy "
                          "(for rocprofv3), then exit")
+    ap.add_argument("--profile-storage", default="fp32", choices=("fp64", "fp32", "fp16s"),
+                    help="storage form of the --profile-steps run (default fp32)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -265,7 +267,8 @@ def main():
     href = 0.1
 
     if args.profile_steps or args.profile_adjoint:
-        sim = Sim(n, n, "fp32", href=href, **p).init(h0, th)
+        prec = "fp32" if args.profile_adjoint else args.profile_storage
+        sim = Sim(n, n, prec, href=0.0 if prec == "fp64" else href, **p).init(h0, th)
         if args.profile_adjoint:
             k = args.profile_adjoint
             cap = torch.empty(k * sim.capture_bytes(), dtype=torch.uint8, device="cuda")
@@ -282,7 +285,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         what = f"reverse pass over {args.profile_adjoint} captured" if args.profile_adjoint else f"{args.profile_steps}"
-        log(f"profile run: {what} fp32 steps at {n}^2 and a 1 GiB copy")
+        log(f"profile run: {what} {prec} steps at {n}^2 and a 1 GiB copy")
         return
 
     ms32, h32, m32 = run_form("fp32", p, h0, th, args.steps, args.warmup, href=href)
