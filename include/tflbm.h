@@ -71,8 +71,11 @@ enum {
  * TFLBM_FP16S stores d_0 in FP32 and the 8 moving deviations in FP16 as
  * d_l * 2^fp16_scale_log2; d_0 absorbs the FP16 rounding so that the stored
  * populations of a site sum to its height.  FP16 keeps about 3 significant
- * digits of d_l: changes of a population far below that (slow, small-amplitude
- * dynamics) are rounded away and the film stagnates. */
+ * digits of d_l, so changes of a population far below |d_l| are rounded
+ * away: on slow dynamics put href at the film height (with href = 0 a
+ * hanging film at h = 1 freezes), and pick the scale so that the moving
+ * deviations stay above FP16's subnormal range (2^-14 after scaling) and
+ * below its largest value (65504). */
 enum { TFLBM_FP64 = 0, TFLBM_FP32 = 1, TFLBM_FP16S = 2 };
 
 typedef struct tflbm_params {

@@ -84,3 +84,37 @@ def test_rayleigh_taylor_mode_growth_fp64_and_fp32():
             assert got64 > 0, (mx, my, got64)
         if n > 1.05 * kc_modes:
             assert got64 < 0, (mx, my, got64)
+
+
+def test_fp16s_hanging_film_follows_fp64_with_reference_height():
+    """FP16S on the hanging film (256^2, modes up to 8, 10000 steps): stored as
+    deviations from the rest equilibrium at the film height (href = 1) it
+    follows the FP64 path, most closely when the FP16 scale lifts the small
+    moving deviations (~1e-9) out of FP16's subnormal range; stored with
+    href = 0 its per-step changes are rounded away and h freezes."""
+    banner("FP16S hanging film 256^2, 10000 steps, href 1 / 0")
+    from paper_1810_07642_amd import Sim
+    n, steps = 256, 10000
+    p, h0, _ = inputs.rayleigh_taylor(n=n, max_mode=8)
+
+    def run(prec, **kw):
+        sim = Sim(n, n, prec, **dict(p, **kw)).init(h0, None)
+        sim.step(steps // 2)
+        mid = sim.height().cpu()
+        sim.step(steps - steps // 2)
+        sim.check()
+        return mid, sim.height().cpu()
+
+    _, ref = run("fp64")
+    amp = float((ref - 1.0).abs().max())
+    errs = {}
+    for s in (12, 18):
+        _, h = run("fp16s", href=1.0, fp16_scale_log2=s)
+        errs[s] = float((h - ref).abs().max()) / amp
+    mid, last = run("fp16s", href=0.0)
+    frozen = float((last - mid).abs().max())
+    moved = float((ref - run("fp64")[0]).abs().max())
+    print(f"error / amplitude: scale 2^12 {errs[12]:.2e}, 2^18 {errs[18]:.2e}; "
+          f"href 0: change over the last {steps // 2} steps {frozen:.1e} (FP64 {moved:.1e})")
+    assert errs[18] <= 1e-4 and errs[12] <= 1e-3
+    assert frozen <= 0.1 * moved
