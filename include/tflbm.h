@@ -68,14 +68,15 @@ enum {
  * flat film); a drop on a precursor film is best served by href = h_*.  For
  * TFLBM_FP32 and TFLBM_FP16S href is rounded to FP32 first.
  *
- * TFLBM_FP16S stores d_0 in FP32 and the 8 moving deviations in FP16 as
- * d_l * 2^fp16_scale_log2; d_0 absorbs the FP16 rounding so that the stored
- * populations of a site sum to its height.  FP16 keeps about 3 significant
- * digits of d_l, so changes of a population far below |d_l| are rounded
- * away: on slow dynamics put href at the film height (with href = 0 a
- * hanging film at h = 1 freezes), and pick the scale so that the moving
- * deviations stay above FP16's subnormal range (2^-14 after scaling) and
- * below its largest value (65504). */
+ * TFLBM_FP16S stores, per site, its height deviation s = h - href in FP32
+ * and each moving population shifted by the rest equilibrium of the site
+ * that emitted it, q_l = (f_l - E_l(h_src)) * 2^fp16_scale_log2, in FP16; the
+ * rest population is implied (the nine values of a site add up to its s),
+ * so mass is held in FP32 and tflbm_mass sums the s.  FP16 keeps about 3
+ * significant digits of q_l: pick the scale so that the moving differences
+ * stay above FP16's subnormal range (2^-14 after scaling) and below its
+ * largest value (65504); h itself has FP32 resolution relative to
+ * |h - href|, so on slow dynamics put href at the film height. */
 enum { TFLBM_FP64 = 0, TFLBM_FP32 = 1, TFLBM_FP16S = 2 };
 
 typedef struct tflbm_params {

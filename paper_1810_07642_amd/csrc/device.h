@@ -43,10 +43,10 @@ template <> struct Form<kF32> {
   static constexpr int V = 2, B = 116, SEG = 116 * 4, GRP = 1408, RB = 3 * GRP;
 };
 template <> struct Form<kF16S> {
-  // rest deviation FP32 (464 B), 8 FP16 segments of 232 B; groups padded to
-  // 1024, 768 and 768 B, plus one unused line: 21 lines, an odd stride (a
-  // power-of-two record stride puts the same segment of every record on the
-  // same few HBM channels)
+  // source height deviation FP32 (464 B), 8 FP16 segments of 232 B; groups
+  // padded to 1024, 768 and 768 B, plus one unused line: 21 lines, an odd
+  // stride (a power-of-two record stride puts the same segment of every
+  // record on the same few HBM channels)
   using T = float;
   static constexpr int V = 2, B = 116, SEG = 116 * 2, RB = 2688;
 };
@@ -221,18 +221,75 @@ template <typename T> __device__ __forceinline__ T ipow(T x, int n) {
 }
 
 // ---- population storage ------------------------------------------------
+// FP16S keeps, per stored site, the height deviation s of the site whose
+// c_ly = 0 populations it holds (its source: the site itself) in FP32, and
+// each moving population as the FP16 difference from the rest equilibrium of
+// its own source (Sec. II, eq. "equilibria" at u = 0):
+//   q_l = (d_l - e_l(s_src)) 2^scale,  e_l(s) = E_l(href + s) - E_l(href),
+// i.e. g s (s + 2 href)/6 on the axes and /24 on the diagonals.  In the
+// "pull in x, push in y" records the entry of population l at (column X,
+// row Y) came from site (X, Y - c_ly), so s_src sits in the same column one
+// row up (c_ly = +1), in the same row (0) or one row down (-1).  The rest
+// deviation is implicit: d_0 = s - sum_{l>=1} (e_l(s) + q_l 2^-scale) over
+// the site's own moving populations (stored at (X, Y + c_ly)), summed in the
+// order l = 1..8, so a site's nine values add up to s and the total mass is
+// the sum of the stored s.  Encoding and decoding below use the same
+// expressions, so a value decoded from memory equals the one the writer
+// formed.
+struct Rest16 {
+  float ax, dg;
+};
+__device__ __forceinline__ Rest16 rest16(float s, float g, float two_href) {
+  const float G = (g * s) * (s + two_href);
+  return {G * (1.0f / 6.0f), G * (1.0f / 24.0f)};
+}
+__device__ __forceinline__ float rest16_l(const Rest16 &e, int l) { return (l & 1) ? e.ax : e.dg; }
+// d_0 of a site from its s and the decoded moving populations it emitted.
+__device__ __forceinline__ float rest16_d0(float s, const float (&d)[9]) {
+  float t = s;
+#pragma unroll
+  for (int l = 1; l < 9; ++l) t -= d[l];
+  return t;
+}
+
+// FP16S: the stored height deviation s of the site at (row y, column c).
+__device__ __forceinline__ float src16_at(const char *buf, int y, int c, const StepArgs &A) {
+  constexpr int B = Form<kF16S>::B;
+  const int blk = c / B, pos = c - blk * B;
+  return ((const float *)(buf + ((size_t)y * A.nblk + blk) * Form<kF16S>::RB))[pos];
+}
+
 // Stored deviation d_l = f_l - E_l(href) of population l at (row y, stored
 // column c), widened to T.
 template <int P>
 __device__ __forceinline__ typename Form<P>::T pop_at(const char *buf, int l, int y, int c, const StepArgs &A) {
   constexpr int B = Form<P>::B;
   const int blk = c / B, pos = c - blk * B;
-  const char *rec = buf + ((size_t)y * A.nblk + blk) * Form<P>::RB + seg_offset<P>(l);
-  if constexpr (P == kF64) return ((const double *)rec)[pos];
-  else if constexpr (P == kF32) return ((const float *)rec)[pos];
+  auto rec = [&](int row, int m) {
+    return buf + ((size_t)row * A.nblk + blk) * Form<P>::RB + seg_offset<P>(m);
+  };
+  if constexpr (P == kF64) return ((const double *)rec(y, l))[pos];
+  else if constexpr (P == kF32) return ((const float *)rec(y, l))[pos];
   else {
-    if (l == 0) return ((const float *)rec)[pos];
-    return dec16(((const __half *)rec)[pos], A.qinv);
+    const float g = (float)A.g, h2 = 2.0f * (float)A.href;
+    const bool g0 = A.g == 0.0;  // as in the step: no rest-equilibrium part to add
+    if (l != 0) {
+      const float q = dec16(((const __half *)rec(y, l))[pos], A.qinv);
+      if (g0) return q;
+      const int ys = wrap(y - kCy[l], A.ny);
+      const Rest16 e = rest16(((const float *)rec(ys, 0))[pos], g, h2);
+      return rest16_l(e, l) + q;
+    }
+    const float s0 = ((const float *)rec(y, 0))[pos];
+    const Rest16 e = rest16(s0, g, h2);
+    float d[9];
+    d[0] = 0.0f;
+#pragma unroll
+    for (int m = 1; m < 9; ++m) {
+      const float q = dec16(((const __half *)rec(wrap(y + kCy[m], A.ny), m))[pos], A.qinv);
+      d[m] = g0 ? q : rest16_l(e, m) + q;
+    }
+    return rest16_d0(s0, d);
   }
 }
 

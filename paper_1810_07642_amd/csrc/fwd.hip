@@ -330,7 +330,6 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
   constexpr int V = Form<P>::V;
   constexpr int B = Form<P>::B;
   constexpr int RB = Form<P>::RB;
-  constexpr int HX = (64 * V - B) / 2;
   const int ny = A.ny;
   const size_t rowB = (size_t)A.nblk * RB;
   const int yN = (y + 1 == ny) ? 0 : y + 1;
@@ -339,16 +338,24 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
                           make_rsrc(A.dst + yN * rowB, (uint32_t)rowB)};  // indexed by c_ly + 1
   const bool pair = L.pair;
   if constexpr (P == kF16S) {
+    // the site's height deviation s, and each moving population as its FP16
+    // difference from the rest equilibrium e_l(s) of this (its source) site
     float rest[V];
     __half q[9][V];
+    const float g16 = (float)A.g, h2 = 2.0f * (float)A.href;
 #pragma unroll
     for (int v = 0; v < V; ++v) rest[v] = hv[v];
+    if (A.g == 0.0) {  // no hydrostatic term: the rest equilibrium has no moving part
 #pragma unroll
-    for (int l = 1; l < 9; ++l) {
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int l = 1; l < 9; ++l) q[l][v] = __float2half_rn(post[l][v] * A.qscale);
+    } else {
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        q[l][v] = __float2half_rn(post[l][v] * A.qscale);
-        rest[v] -= dec16(q[l][v], A.qinv);  // rest deviation absorbs the rounding
+        const Rest16 e = rest16(hv[v], g16, h2);
+#pragma unroll
+        for (int l = 1; l < 9; ++l) q[l][v] = __float2half_rn((post[l][v] - rest16_l(e, l)) * A.qscale);
       }
     }
     if (L.fast_store) {
@@ -417,21 +424,67 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
 }
 
 // FP16S storage round trip of one row of post-collision deviations (what a
-// store followed by a load would give): moving deviations rounded to FP16 in
-// the scaled form, rest deviation dh - sum of the decoded moving ones.
+// store followed by a load would give): moving deviations rounded to FP16 as
+// differences from the rest equilibrium of the writing site, rest deviation
+// implied by its height deviation hv (rest16_d0).
 template <int V>
 __device__ __forceinline__ void fp16s_roundtrip(float (&post)[9][V], const float (&hv)[V], const StepArgs &A) {
+  const float g16 = (float)A.g, h2 = 2.0f * (float)A.href;
+  const bool g0 = A.g == 0.0;
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    float rest = hv[v];
+    float d[9];
+    d[0] = 0.0f;
+    if (g0) {
 #pragma unroll
-    for (int l = 1; l < 9; ++l) {
-      const __half q = __float2half_rn(post[l][v] * A.qscale);
-      const float d = dec16(q, A.qinv);
-      rest -= d;
-      post[l][v] = d;
+      for (int l = 1; l < 9; ++l) d[l] = dec16(__float2half_rn(post[l][v] * A.qscale), A.qinv);
+    } else {
+      const Rest16 e = rest16(hv[v], g16, h2);
+#pragma unroll
+      for (int l = 1; l < 9; ++l) {
+        const float el = rest16_l(e, l);
+        d[l] = el + dec16(__float2half_rn((post[l][v] - el) * A.qscale), A.qinv);
+      }
     }
-    post[0][v] = rest;
+#pragma unroll
+    for (int l = 1; l < 9; ++l) post[l][v] = d[l];
+    post[0][v] = rest16_d0(hv[v], d);
+  }
+}
+
+// FP16S decoding of stored row r (raw values: slot 0 the site's s, slots
+// l >= 1 the scaled-back FP16 differences) into deviations, per stored column:
+// moving populations add the rest equilibrium of their source row (r for
+// c_ly = 0, r - 1 for +1, r + 1 for -1); the rest deviation of row r's sites
+// is implied by their s and the moving populations they emitted, which sit in
+// rows r (c_ly = 0), r + 1 (+1) and r - 1 (-1, kept from the previous row as
+// cq together with its s, cs).
+template <int V>
+__device__ __forceinline__ void fp16s_decode(const float (&cur)[9][V], const float (&nxt)[9][V], const float (&cs)[V],
+                                             const float (&cq)[3][V], const StepArgs &A, float (&d)[9][V]) {
+  const float g16 = (float)A.g, h2 = 2.0f * (float)A.href;
+  const bool g0 = A.g == 0.0;  // no hydrostatic term: the values are the differences themselves
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    float t[9];
+    t[0] = 0.0f;
+    if (g0) {
+#pragma unroll
+      for (int l = 1; l < 9; ++l) {
+        d[l][v] = cur[l][v];
+        t[l] = kCy[l] == 0 ? cur[l][v] : (kCy[l] > 0 ? nxt[l][v] : cq[l >= 6 ? l - 6 : 0][v]);
+      }
+    } else {
+      const Rest16 em = rest16(cs[v], g16, h2), e0 = rest16(cur[0][v], g16, h2), ep = rest16(nxt[0][v], g16, h2);
+#pragma unroll
+      for (int l = 1; l < 9; ++l) {
+        const Rest16 &e = kCy[l] == 0 ? e0 : (kCy[l] > 0 ? em : ep);
+        d[l][v] = rest16_l(e, l) + cur[l][v];
+        const float qo = kCy[l] == 0 ? cur[l][v] : (kCy[l] > 0 ? nxt[l][v] : cq[l >= 6 ? l - 6 : 0][v]);
+        t[l] = rest16_l(e0, l) + qo;
+      }
+    }
+    d[0][v] = rest16_d0(cur[0][v], t);
   }
 }
 
@@ -546,19 +599,50 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   T fa[9][V], fb[9][V];  // stored values of rows r (being consumed) and r + 1
   int ry = wrap(y0 - HALO, ny);                          // row r of stage 0
   int rpre = ry + 2 >= ny ? (ry + 2) % ny : ry + 2;      // row r + 2
+  // FP16S decodes row r with rows r - 1 and r + 1 (fp16s_decode): the row
+  // above the first is read for its s and q_6..q_8, and one row past the
+  // last (KL = K + 1 rows are loaded after it)
+  T cs[V], cq[3][V];
+  constexpr int KX = P == kF16S ? 1 : 0;
+  const int KL = K + KX;
+  if constexpr (P == kF16S) {
+    T fp[9][V];
+    load_row<P>(rsrc_src(ry == 0 ? ny - 1 : ry - 1), L, fp, A);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      cs[v] = fp[0][v];
+      cq[0][v] = fp[6][v];
+      cq[1][v] = fp[7][v];
+      cq[2][v] = fp[8][v];
+    }
+  }
   load_row<P>(rsrc_src(ry), L, fa, A);
-  if (K > 1) {
+  if (KL > 1) {
     const int r1 = ry + 1 == ny ? 0 : ry + 1;
     load_row<P>(rsrc_src(r1), L, fb, A);
   }
 
-  auto iteration = [&](int k, T(&cur)[9][V]) {
+  auto iteration = [&](int k, T(&cur)[9][V], const T(&nxt)[9][V]) {
     T f[9][V], f2[9][V];
+    if constexpr (P == kF16S) {
+      T d[9][V];
+      fp16s_decode<V>(cur, nxt, cs, cq, A, d);
 #pragma unroll
-    for (int l = 0; l < 9; ++l) shift_x<T, V>(l, cur[l], f[l]);
+      for (int v = 0; v < V; ++v) {
+        cs[v] = cur[0][v];
+        cq[0][v] = cur[6][v];
+        cq[1][v] = cur[7][v];
+        cq[2][v] = cur[8][v];
+      }
+#pragma unroll
+      for (int l = 0; l < 9; ++l) shift_x<T, V>(l, d[l], f[l]);
+    } else {
+#pragma unroll
+      for (int l = 0; l < 9; ++l) shift_x<T, V>(l, cur[l], f[l]);
+    }
     S0.ingest(k, ry, f, f2, L, A, lane);
     // prefetch row r + 2 into the registers just freed
-    if (k + 2 < K) load_row<P>(rsrc_src(rpre), L, cur, A);
+    if (k + 2 < KL) load_row<P>(rsrc_src(rpre), L, cur, A);
     T post[9][V], hv[V], jxv[V], jyv[V];
     if (S0.finish(k, f2, post, hv, jxv, jyv, C, L, bad)) {
       const int q = y0 - HALO + k - 2;  // row of the post-collision values (unwrapped)
@@ -615,8 +699,8 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   };
 
   for (int k = 0; k < K; k += 2) {
-    iteration(k, fa);
-    if (k + 1 < K) iteration(k + 1, fb);
+    iteration(k, fa, fb);
+    if (k + 1 < K) iteration(k + 1, fb, fa);
   }
 
   const unsigned long long m = __ballot(bad);
@@ -652,13 +736,28 @@ __global__ void init_kernel(StepArgs A, const double *h0, const double *theta, d
   if constexpr (P == kF64 || P == kF32) {
     for (int l = 0; l < 9; ++l) *(T *)pop_ptr<P>(A.dst, l, y, wrap(x - kCx[l], A.nx), A) = (T)e[l];
   } else {
-    double sumd = 0.0;
+    // FP16S: the state is written as if emitted by a step: site (xs, ys)'s s
+    // is the sum of the deviations it "emitted", its rest population and the
+    // moving ones that sit at its neighbours (e_l of their h0), and each
+    // moving population is stored as its FP16 difference from the rest
+    // equilibrium of its source site.
+    auto eq_dev = [&](int xs, int ys, int l) {
+      const double hh = h0[(size_t)wrap(ys, A.ny) * A.nx + wrap(xs, A.nx)];
+      const double dd = hh - A.href, qq = A.g * dd * (hh + A.href);
+      return l == 0 ? dd - qq * (5.0 / 6.0) : ((l & 1) ? qq * (1.0 / 6.0) : qq * (1.0 / 24.0));
+    };
+    auto s_of = [&](int xs, int ys) {
+      double sum = eq_dev(xs, ys, 0);
+      for (int m = 1; m < 9; ++m) sum += eq_dev(xs + kCx[m], ys + kCy[m], m);
+      return (float)sum;
+    };
+    const float g16 = (float)A.g, h2 = 2.0f * (float)A.href;
+    *(float *)pop_ptr<P>(A.dst, 0, y, x, A) = s_of(x, y);
     for (int l = 1; l < 9; ++l) {
-      const __half dq = __float2half_rn((float)e[l] * A.qscale);
+      const Rest16 es = rest16(s_of(x - kCx[l], y - kCy[l]), g16, h2);
+      const __half dq = __float2half_rn(((float)e[l] - rest16_l(es, l)) * A.qscale);
       *(__half *)pop_ptr<P>(A.dst, l, y, wrap(x - kCx[l], A.nx), A) = dq;
-      sumd += (double)dec16(dq, A.qinv);
     }
-    *(float *)pop_ptr<P>(A.dst, 0, y, x, A) = (float)(dh - sumd);
   }
   if (theta != nullptr) {
     const double th = theta[(size_t)y * A.nx + x];
@@ -700,9 +799,13 @@ __global__ __launch_bounds__(256) void mass_partial_kernel(StepArgs A, double *p
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int y = (int)(i / A.nx), c = (int)(i % A.nx);
-    double s = 0.0;
-    for (int l = 0; l < 9; ++l) s += (double)pop_at<P>(A.src, l, y, c, A);
-    acc += s;
+    if constexpr (P == kF16S) {
+      acc += (double)src16_at(A.src, y, c, A);  // a site's nine deviations add up to its s
+    } else {
+      double s = 0.0;
+      for (int l = 0; l < 9; ++l) s += (double)pop_at<P>(A.src, l, y, c, A);
+      acc += s;
+    }
   }
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;

@@ -209,13 +209,14 @@ def test_nonfinite_and_nonpositive_heights_flagged():
 
 
 def test_fp16s_scale_overflow_is_flagged():
-    """A scale too large for the stored deviations overflows FP16 (axis
-    populations g h^2/6 = 7.5e-3 at h = 0.3, g = 0.5, times 2^24 > 65504): the
-    next step meets a non-finite height and the status says so; the same run
-    at the default scale 2^12 stays finite."""
+    """A scale too large for the stored FP16 differences overflows: with h0 in
+    0.3 .. 0.6 and g = 0.5 neighbouring rest equilibria differ by up to
+    g (0.6^2 - 0.3^2)/6 = 2.3e-2, times 2^24 > 65504, so the state holds
+    infinities, the next step meets a non-finite height and the status says
+    so; the same run at the default scale 2^12 stays finite."""
     from paper_1810_07642_amd import Sim, TFLBMError
     from paper_1810_07642_amd._lib import TFLBM_ENONFINITE
-    h0 = torch.full((16, 70), 0.3, dtype=torch.float64)
+    h0, _ = random_case(16, 70, 5)
     for s, bad in ((24, True), (12, False)):
         sim = Sim(70, 16, "fp16s", hstar=0.1, g=0.5, fp16_scale_log2=s).init(h0, None)
         sim.step(2)

@@ -87,11 +87,14 @@ def test_rayleigh_taylor_mode_growth_fp64_and_fp32():
 
 
 def test_fp16s_hanging_film_follows_fp64_with_reference_height():
-    """FP16S on the hanging film (256^2, modes up to 8, 10000 steps): stored as
-    deviations from the rest equilibrium at the film height (href = 1) it
-    follows the FP64 path, most closely when the FP16 scale lifts the small
-    moving deviations (~1e-9) out of FP16's subnormal range; stored with
-    href = 0 its per-step changes are rounded away and h freezes."""
+    """FP16S on the hanging film (256^2, modes up to 8, 10000 steps): each
+    site's height deviation from href is held in FP32 and the moving
+    populations as FP16 differences from their source's rest equilibrium.
+    With href = 1 (the film height) the run follows the FP64 path, most
+    closely when the FP16 scale lifts the small differences (~1e-9) out of
+    FP16's subnormal range; with href = 0 the FP32 height h ~ 1 cannot carry
+    the 1e-10 per-step changes (as for FP32 storage) and the error is at least
+    ten times larger."""
     banner("FP16S hanging film 256^2, 10000 steps, href 1 / 0")
     from paper_1810_07642_amd import Sim
     n, steps = 256, 10000
@@ -99,22 +102,16 @@ def test_fp16s_hanging_film_follows_fp64_with_reference_height():
 
     def run(prec, **kw):
         sim = Sim(n, n, prec, **dict(p, **kw)).init(h0, None)
-        sim.step(steps // 2)
-        mid = sim.height().cpu()
-        sim.step(steps - steps // 2)
+        sim.step(steps)
         sim.check()
-        return mid, sim.height().cpu()
+        return sim.height().cpu()
 
-    _, ref = run("fp64")
+    ref = run("fp64")
     amp = float((ref - 1.0).abs().max())
     errs = {}
-    for s in (12, 18):
-        _, h = run("fp16s", href=1.0, fp16_scale_log2=s)
-        errs[s] = float((h - ref).abs().max()) / amp
-    mid, last = run("fp16s", href=0.0)
-    frozen = float((last - mid).abs().max())
-    moved = float((ref - run("fp64")[0]).abs().max())
-    print(f"error / amplitude: scale 2^12 {errs[12]:.2e}, 2^18 {errs[18]:.2e}; "
-          f"href 0: change over the last {steps // 2} steps {frozen:.1e} (FP64 {moved:.1e})")
-    assert errs[18] <= 1e-4 and errs[12] <= 1e-3
-    assert frozen <= 0.1 * moved
+    for href, s in ((1.0, 12), (1.0, 18), (0.0, 18)):
+        h = run("fp16s", href=href, fp16_scale_log2=s)
+        errs[(href, s)] = float((h - ref).abs().max()) / amp
+    print("error / amplitude: " + ", ".join(f"href {k[0]} scale 2^{k[1]}: {v:.2e}" for k, v in errs.items()))
+    assert errs[(1.0, 18)] <= 1e-4 and errs[(1.0, 12)] <= 1e-3
+    assert errs[(0.0, 18)] >= 10 * errs[(1.0, 18)]
