@@ -70,8 +70,12 @@ void plan_launches(tflbm_sim *s) {
   // that a tile's time is its chain of rows, 5 for one step against 11 per
   // two fused steps, each of those twice the work.  Measured per step at FP32:
   // 128^2 5.4 vs 6.4 us, 256^2 6.0 vs 6.8, 512^2 9.2 vs 9.4; from 768^2 on
-  // the fused pass wins.
-  s->fuse_fits = (int64_t)s->nstrips * ny > (int64_t)occ1 * cus;
+  // the fused pass wins.  FP16S, whose rows take longer to decode and whose
+  // one-step kernel keeps two wavefronts per SIMD instead of three, gains
+  // from one step per pass up to three such rounds (512^2: 10.9 vs 12.9 us,
+  // 768^2: 13.7 vs 15.1; 1024^2: 19.6 vs 19.1).
+  const int rounds = s->p.prec == kF16S ? 3 : 1;
+  s->fuse_fits = (int64_t)s->nstrips * ny > (int64_t)rounds * occ1 * cus;
   // Reverse steps: at most two resident wavefronts per SIMD are planned for
   // (eight per CU).  At 4096^2 FP32 the one-step kernel, which fits three,
   // ran 9% faster with chunks sized for two than for three.
