@@ -66,7 +66,7 @@ template <int P> __host__ __device__ constexpr int seg_offset(int l) {
   if constexpr (P == kF64 || P == kF32) {
     return (kSlot[l] / 3) * Form<P>::GRP + (kSlot[l] % 3) * Form<P>::SEG;
   } else {
-    // FP16S: rest deviation FP32 at 0, FP16 slots 1-2 at 464, slots 3-5 at
+    // FP16S: site height deviation FP32 at 0, FP16 slots 1-2 at 464, slots 3-5 at
     // 1024, slots 6-8 at 1792 (each c_ly group starts on a 128-byte line)
     constexpr int S = Form<kF16S>::SEG;
     const int s = kSlot[l];
