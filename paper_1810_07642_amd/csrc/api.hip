@@ -55,8 +55,9 @@ void plan_launches(tflbm_sim *s) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
   }
   const int ny = s->p.ny;
-  int occ1 = step_blocks_per_cu(s->p.prec, s->kfield, 1);
-  int occ2 = step_blocks_per_cu(s->p.prec, s->kfield, 2);
+  const bool g0 = s->p.g == 0.0;
+  int occ1 = step_blocks_per_cu(s->p.prec, s->kfield, 1, g0);
+  int occ2 = step_blocks_per_cu(s->p.prec, s->kfield, 2, g0);
   if (occ1 <= 0) occ1 = 8;
   if (occ2 <= 0) occ2 = 8;
   s->rows = choose_rows(ny, s->nstrips, occ1 * cus, kMinRowsStep, "TFLBM_ROWS");
@@ -70,12 +71,12 @@ void plan_launches(tflbm_sim *s) {
   // that a tile's time is its chain of rows, 5 for one step against 11 per
   // two fused steps, each of those twice the work.  Measured per step at FP32:
   // 128^2 5.4 vs 6.4 us, 256^2 6.0 vs 6.8, 512^2 9.2 vs 9.4; from 768^2 on
-  // the fused pass wins.  FP16S, whose rows take longer to decode and whose
-  // one-step kernel keeps two wavefronts per SIMD instead of three, gains
-  // from one step per pass up to three such rounds (512^2: 10.9 vs 12.9 us,
-  // 768^2: 13.7 vs 15.1; 1024^2: 19.6 vs 19.1).
-  const int rounds = s->p.prec == kF16S ? 3 : 1;
-  s->fuse_fits = (int64_t)s->nstrips * ny > (int64_t)rounds * occ1 * cus;
+  // the fused pass wins.  FP16S, whose rows take longer to decode, gains from
+  // one step per pass up to about 24 one-row tiles per CU (g = 0, per step:
+  // 512^2 10.0 vs 12.0 us, 768^2 12.4 vs 14.1; 1024^2 18.5 vs 17.9; with
+  // g != 0 likewise 512^2 10.9 vs 12.9, 768^2 13.7 vs 15.1).
+  const int64_t one_row_tiles = s->p.prec == kF16S ? 24LL * cus : (int64_t)occ1 * cus;
+  s->fuse_fits = (int64_t)s->nstrips * ny > one_row_tiles;
   // Reverse steps: at most two resident wavefronts per SIMD are planned for
   // (eight per CU).  At 4096^2 FP32 the one-step kernel, which fits three,
   // ran 9% faster with chunks sized for two than for three.

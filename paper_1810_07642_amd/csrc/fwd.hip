@@ -323,7 +323,7 @@ template <int P, bool KF> struct Stage {
 
 // Stores the post-collision deviations of row y (values at the lane's own
 // columns, hv = dh of the row) into stored column x of rows y + c_ly.
-template <int P>
+template <int P, bool G0 = false>
 __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typename Form<P>::T (&post)[9][Form<P>::V],
                                           const typename Form<P>::T (&hv)[Form<P>::V], const Lane<P> &L, int x0,
                                           int xend, int lane) {
@@ -345,7 +345,7 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
     const float g16 = (float)A.g, h2 = 2.0f * (float)A.href;
 #pragma unroll
     for (int v = 0; v < V; ++v) rest[v] = hv[v];
-    if (A.g == 0.0) {  // no hydrostatic term: the rest equilibrium has no moving part
+    if constexpr (G0) {  // g = 0: the rest equilibrium has no moving part
 #pragma unroll
       for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -427,15 +427,14 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
 // store followed by a load would give): moving deviations rounded to FP16 as
 // differences from the rest equilibrium of the writing site, rest deviation
 // implied by its height deviation hv (rest16_d0).
-template <int V>
+template <int V, bool G0>
 __device__ __forceinline__ void fp16s_roundtrip(float (&post)[9][V], const float (&hv)[V], const StepArgs &A) {
   const float g16 = (float)A.g, h2 = 2.0f * (float)A.href;
-  const bool g0 = A.g == 0.0;
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     float d[9];
     d[0] = 0.0f;
-    if (g0) {
+    if constexpr (G0) {
 #pragma unroll
       for (int l = 1; l < 9; ++l) d[l] = dec16(__float2half_rn(post[l][v] * A.qscale), A.qinv);
     } else {
@@ -459,16 +458,15 @@ __device__ __forceinline__ void fp16s_roundtrip(float (&post)[9][V], const float
 // is implied by their s and the moving populations they emitted, which sit in
 // rows r (c_ly = 0), r + 1 (+1) and r - 1 (-1, kept from the previous row as
 // cq together with its s, cs).
-template <int V>
+template <int V, bool G0>
 __device__ __forceinline__ void fp16s_decode(const float (&cur)[9][V], const float (&nxt)[9][V], const float (&cs)[V],
                                              const float (&cq)[3][V], const StepArgs &A, float (&d)[9][V]) {
   const float g16 = (float)A.g, h2 = 2.0f * (float)A.href;
-  const bool g0 = A.g == 0.0;  // no hydrostatic term: the values are the differences themselves
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     float t[9];
     t[0] = 0.0f;
-    if (g0) {
+    if constexpr (G0) {  // g = 0: the values are the differences themselves
 #pragma unroll
       for (int l = 1; l < 9; ++l) {
         d[l][v] = cur[l][v];
@@ -533,7 +531,9 @@ __device__ __forceinline__ void capture_row(const StepArgs &A, char *base, int q
 // reads 2 + 3 (NS - 1) halo rows above and below.  With CAP the moments of
 // each step's pre-collision state on the tile's own rows go to the capture:
 // step t at A.capture, step t + 1 one capture block later.
-template <int P, bool KF, bool CAP, int NS>
+// G0 (FP16S only): the launch has g = 0, so the rest equilibrium of the
+// FP16S shift has no moving part and its code is left out.
+template <int P, bool KF, bool CAP, int NS, bool G0 = false>
 __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   using T = typename Form<P>::T;
   constexpr int V = Form<P>::V;
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
     T f[9][V], f2[9][V];
     if constexpr (P == kF16S) {
       T d[9][V];
-      fp16s_decode<V>(cur, nxt, cs, cq, A, d);
+      fp16s_decode<V, G0>(cur, nxt, cs, cq, A, d);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         cs[v] = cur[0][v];
@@ -647,7 +647,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
     if (S0.finish(k, f2, post, hv, jxv, jyv, C, L, bad)) {
       const int q = y0 - HALO + k - 2;  // row of the post-collision values (unwrapped)
       if constexpr (NS == 1) {
-        store_row<P>(A, q, post, hv, L, x0, xend, lane);
+        store_row<P, G0>(A, q, post, hv, L, x0, xend, lane);
         if constexpr (CAP) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane);
       } else {
         // row q - 1 of the next step is complete: c_ly = +1 populations from
@@ -656,7 +656,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
         if constexpr (CAP) {
           if (q >= y0 && q < yend) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane);
         }
-        if constexpr (P == kF16S) fp16s_roundtrip<V>(post, hv, A);  // as if stored and reloaded
+        if constexpr (P == kF16S) fp16s_roundtrip<V, G0>(post, hv, A);  // as if stored and reloaded
         T g[9][V];
         shift_x<T, V>(6, post[6], g[6]);
         shift_x<T, V>(7, post[7], g[7]);
@@ -686,7 +686,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
           S1.ingest(j, rowB1, g, g2, L, A, lane);
           T post2[9][V], hv2[V], jx2[V], jy2[V];
           if (S1.finish(j, g2, post2, hv2, jx2, jy2, C, L, bad)) {
-            store_row<P>(A, y0 - 4 + j, post2, hv2, L, x0, xend, lane);
+            store_row<P, G0>(A, y0 - 4 + j, post2, hv2, L, x0, xend, lane);
             if constexpr (CAP)
               capture_row<P>(A, A.capture + (size_t)ny * A.nblk * cap_record_bytes<P>(), y0 - 4 + j, hv2, jx2, jy2, L,
                              C.href, x0, xend, lane);
@@ -824,26 +824,27 @@ __global__ __launch_bounds__(256) void mass_final_kernel(const double *partial, 
 }
 
 // ---- launchers -----------------------------------------------------------------
+template <int P, int NS, bool G0>
+static void launch_step_v(const StepArgs &A, bool kf, bool cap, hipStream_t s) {
+  const dim3 grid(8 * A.per_xcd), block(64);
+  if (kf) {
+    if (cap) step_kernel<P, true, true, NS, G0><<<grid, block, 0, s>>>(A);
+    else step_kernel<P, true, false, NS, G0><<<grid, block, 0, s>>>(A);
+  } else {
+    if (cap) step_kernel<P, false, true, NS, G0><<<grid, block, 0, s>>>(A);
+    else step_kernel<P, false, false, NS, G0><<<grid, block, 0, s>>>(A);
+  }
+}
+
 template <int P, int NS>
 static hipError_t launch_step_p(const StepArgs &A, bool kf, bool cap, hipStream_t s) {
-  const dim3 grid(8 * A.per_xcd), block(64);
-  if constexpr (NS == 1) {
-    if (kf) {
-      if (cap) step_kernel<P, true, true, 1><<<grid, block, 0, s>>>(A);
-      else step_kernel<P, true, false, 1><<<grid, block, 0, s>>>(A);
-    } else {
-      if (cap) step_kernel<P, false, true, 1><<<grid, block, 0, s>>>(A);
-      else step_kernel<P, false, false, 1><<<grid, block, 0, s>>>(A);
-    }
-  } else {
-    if (kf) {
-      if (cap) step_kernel<P, true, true, 2><<<grid, block, 0, s>>>(A);
-      else step_kernel<P, true, false, 2><<<grid, block, 0, s>>>(A);
-    } else {
-      if (cap) step_kernel<P, false, true, 2><<<grid, block, 0, s>>>(A);
-      else step_kernel<P, false, false, 2><<<grid, block, 0, s>>>(A);
+  if constexpr (P == kF16S) {
+    if (A.g == 0.0) {
+      launch_step_v<P, NS, true>(A, kf, cap, s);
+      return hipGetLastError();
     }
   }
+  launch_step_v<P, NS, false>(A, kf, cap, s);
   return hipGetLastError();
 }
 
@@ -863,25 +864,27 @@ hipError_t launch_step2(int prec, const StepArgs &A, bool kf, bool cap, hipStrea
   }
 }
 
-template <int P>
-static int occupancy_p(bool kf, int ns) {
+template <int P, int NS, bool G0>
+static int occupancy_v(bool kf) {
   int n = 0;
-  hipError_t e;
-  if (ns == 2) {
-    e = kf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, true, false, 2>, 64, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, false, false, 2>, 64, 0);
-  } else {
-    e = kf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, true, false, 1>, 64, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, false, false, 1>, 64, 0);
-  }
+  const hipError_t e = kf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, true, false, NS, G0>, 64, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, false, false, NS, G0>, 64, 0);
   return e == hipSuccess ? n : 0;
 }
 
-int step_blocks_per_cu(int prec, bool kf, int ns) {
+template <int P>
+static int occupancy_p(bool kf, int ns, bool g0) {
+  if constexpr (P == kF16S) {
+    if (g0) return ns == 2 ? occupancy_v<P, 2, true>(kf) : occupancy_v<P, 1, true>(kf);
+  }
+  return ns == 2 ? occupancy_v<P, 2, false>(kf) : occupancy_v<P, 1, false>(kf);
+}
+
+int step_blocks_per_cu(int prec, bool kf, int ns, bool g0) {
   switch (prec) {
-    case kF64: return occupancy_p<kF64>(kf, ns);
-    case kF32: return occupancy_p<kF32>(kf, ns);
-    default: return occupancy_p<kF16S>(kf, ns);
+    case kF64: return occupancy_p<kF64>(kf, ns, g0);
+    case kF32: return occupancy_p<kF32>(kf, ns, g0);
+    default: return occupancy_p<kF16S>(kf, ns, g0);
   }
 }
 

@@ -18,7 +18,7 @@ int record_bytes(int prec);
 
 hipError_t launch_step(int prec, const StepArgs &A, bool kfield, bool capture, hipStream_t s);
 // Resident one-wavefront workgroups per CU of the step kernel (0 if unknown).
-int step_blocks_per_cu(int prec, bool kfield, int ns);
+int step_blocks_per_cu(int prec, bool kfield, int ns, bool g0);
 // Two fused time steps in one pass (src at time t, dst at time t + 2).
 hipError_t launch_step2(int prec, const StepArgs &A, bool kfield, bool capture, hipStream_t s);
 hipError_t launch_init(int prec, const StepArgs &A, const double *h0, const double *theta, double kconst,

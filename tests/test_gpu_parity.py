@@ -249,16 +249,18 @@ def test_checkpoint_restore_is_bitwise_and_runs_are_deterministic():
         assert torch.equal(c.height().cpu(), ha)
 
 
+@pytest.mark.parametrize("g", [1e-3, 0.0])
 @pytest.mark.parametrize("href", [0.0, 0.45])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
-def test_fused_steps_equal_single_steps_bitwise(prec, href):
+def test_fused_steps_equal_single_steps_bitwise(prec, href, g):
     """Two time steps fused in one pass give the same bits as two passes of
     one step (same arithmetic, intermediate rows kept on chip), on ragged,
     odd and degenerate grids, with an odd step count (fused pairs plus one
-    single step)."""
+    single step); g = 0 also runs the FP16S kernels without the hydrostatic
+    part of the shift."""
     import os
     from paper_1810_07642_amd import Sim
-    p = dict(tau=0.9, gamma=0.01, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5, ay=-1e-5, href=href)
+    p = dict(tau=0.9, gamma=0.01, g=g, hstar=0.1, delta=1.0, ax=1e-5, ay=-1e-5, href=href)
     for (ny, nx) in [(70, 150), (23, 37), (1, 1), (6, 300), (130, 97)]:
         h0, th = random_case(ny, nx, 41)
         states = []
@@ -275,14 +277,15 @@ def test_fused_steps_equal_single_steps_bitwise(prec, href):
             assert torch.equal(a, b), (prec, href, ny, nx)
 
 
+@pytest.mark.parametrize("g", [1e-3, 0.0])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
-def test_fused_capture_equals_single_step_capture_bitwise(prec):
+def test_fused_capture_equals_single_step_capture_bitwise(prec, g):
     """The capture of the reverse sweep (h, jx, jy of every step) written by
     the fused two-step pass equals the one written step by step, and the
     final state too, on ragged grids with an odd step count."""
     import os
     from paper_1810_07642_amd import Sim
-    p = dict(tau=0.9, gamma=0.01, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5, ay=-1e-5, href=0.4)
+    p = dict(tau=0.9, gamma=0.01, g=g, hstar=0.1, delta=1.0, ax=1e-5, ay=-1e-5, href=0.4)
     for (ny, nx) in [(70, 150), (23, 37), (6, 300)]:
         h0, th = random_case(ny, nx, 43)
         out = []
