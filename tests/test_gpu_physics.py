@@ -115,3 +115,33 @@ def test_fp16s_hanging_film_follows_fp64_with_reference_height():
     print("error / amplitude: " + ", ".join(f"href {k[0]} scale 2^{k[1]}: {v:.2e}" for k, v in errs.items()))
     assert errs[(1.0, 18)] <= 1e-4 and errs[(1.0, 12)] <= 1e-3
     assert errs[(0.0, 18)] >= 10 * errs[(1.0, 18)]
+
+
+@pytest.mark.parametrize("theta_deg", [20.0, 30.0])
+def test_relaxed_drop_contact_angle_all_forms(theta_deg):
+    """The sessile drop of Sec. III B on the GPU (128^2, base radius 28, apex
+    12 on h_* = 0.4, 40000 steps): its angle falls monotonically to the one
+    set through kappa, within the 8 % the oracle test allows (lubrication puts
+    the apparent angle a few percent under theta), and the FP32 and FP16S
+    forms (stored about h_ref = h_*) reach the FP64 angle within 1e-3 of it."""
+    from paper_1810_07642_amd import Sim
+    from physics import contact_angle
+    theta = math.radians(theta_deg)
+    banner(f"relaxed drop 128^2, theta {theta_deg} deg, all forms")
+    p, h0, th = inputs.sessile_drop(n=128, base_radius=28.0, apex=12.0, hstar=0.4, theta=theta)
+    angles, history = {}, []
+    for prec in ("fp64", "fp32", "fp16s"):
+        kw = dict(p) if prec == "fp64" else dict(p, href=0.4)
+        sim = Sim(128, 128, prec, **kw).init(h0, th)
+        for _ in range(8):
+            sim.step(5000)
+            if prec == "fp64":
+                history.append(contact_angle(sim.height().cpu().numpy(), 0.4))
+        sim.check()
+        angles[prec] = contact_angle(sim.height().cpu().numpy(), 0.4)
+    print({k: round(math.degrees(v), 4) for k, v in angles.items()}, "target", theta_deg,
+          "FP64 history", [round(math.degrees(a), 3) for a in history])
+    assert all(b < a + 1e-9 for a, b in zip(history, history[1:]))
+    assert abs(angles["fp64"] - theta) <= 0.08 * theta
+    for prec in ("fp32", "fp16s"):
+        assert abs(angles[prec] - angles["fp64"]) <= 1e-3 * angles["fp64"]
