@@ -4,9 +4,10 @@
 gamma = 0.01, tau = 1, delta = 0.5, no wetting term (Sec. III A), 50000 steps.  The noise
 keeps Fourier modes up to 64 of 256: the checkerboard mode of the scheme grows by
 2.7e-4 per step for this g (test_checkerboard_mode_unstable_for_negative_gravity) and from
-unfiltered 1e-3 noise drives h to zero near step 34000.  Both forms store deviations from
+unfiltered 1e-3 noise drives h to zero near step 34000.  All forms store deviations from
 the rest equilibrium at href = 1 (FP32 with href = 0 cannot resolve the 1e-10 per-step
-changes of h near 1, and its rounding seeds the unstable band).  In the
+changes of h near 1, and its rounding seeds the unstable band); FP16S holds h - href in
+FP32 and the moving populations at scale 2^18.  In the
 linear regime every Fourier mode of h grows at the rate of the slowest eigenvalue of the
 one-step propagator of the linearised scheme (tests/physics.py, pinned on the CPU against
 the oracle and against the thin-film law eq. "RTgrowth" with its discrete corrections).
@@ -27,10 +28,10 @@ pytestmark = pytest.mark.gpu
 N, T1, T2 = 512, 1000, 50000
 
 
-def growth_rates(prec):
+def growth_rates(prec, **extra):
     from paper_1810_07642_amd import Sim
     p, h0, th = inputs.rayleigh_taylor(n=N, max_mode=64)
-    sim = Sim(N, N, prec, href=1.0, **p).init(h0, th)
+    sim = Sim(N, N, prec, href=1.0, **dict(p, **extra)).init(h0, th)
     sim.step(T1)
     h1 = sim.height().cpu()
     sim.step(T2 - T1)
@@ -47,11 +48,13 @@ def lb_rate(kx, ky, p):
     return math.log(abs(ev[np.argmin(np.abs(np.abs(ev) - 1.0))]))
 
 
-def test_rayleigh_taylor_mode_growth_fp64_and_fp32():
-    banner("RT 512^2 x 50000, fp64 and fp32")
+def test_rayleigh_taylor_mode_growth_all_forms():
+    """The FP16S form (href = 1, scale 2^18: reading on FP16's subnormal
+    range) is held to the same tolerance as FP32."""
+    banner("RT 512^2 x 50000, fp64, fp32 and fp16s")
     res = {}
-    for prec in ("fp64", "fp32"):
-        p, sig, h = growth_rates(prec)
+    for prec, extra in (("fp64", {}), ("fp32", {}), ("fp16s", {"fp16_scale_log2": 18})):
+        p, sig, h = growth_rates(prec, **extra)
         res[prec] = (sig, h)
     p = inputs.rayleigh_taylor(n=8)[0]
     nu = (p["tau"] - 0.5) / 3.0
@@ -67,19 +70,22 @@ def test_rayleigh_taylor_mode_growth_fp64_and_fp32():
             lub = lubrication_growth(k, 1.0, abs(p["g"]), p["gamma"], nu, p["delta"])
             got64 = float(res["fp64"][0][my, mx])
             got32 = float(res["fp32"][0][my, mx])
-            rows.append((n, mx, my, expect, lub, got64, got32))
-    print("mode   mx my  sigma_LB     sigma_lub    measured64   measured32")
+            got16 = float(res["fp16s"][0][my, mx])
+            rows.append((n, mx, my, expect, lub, got64, got32, got16))
+    print("mode   mx my  sigma_LB     sigma_lub    measured64   measured32   measured16")
     for r in sorted(rows):
-        print("%5.2f %3d %2d %+.4e %+.4e %+.4e %+.4e" % r)
-    h64, h32 = res["fp64"][1], res["fp32"][1]
-    print(f"fp32 vs fp64 final h: max |dh| = {float((h32 - h64).abs().max()):.3e}", flush=True)
-    for n, mx, my, expect, lub, got64, got32 in rows:
+        print("%5.2f %3d %2d %+.4e %+.4e %+.4e %+.4e %+.4e" % r)
+    h64, h32, h16 = res["fp64"][1], res["fp32"][1], res["fp16s"][1]
+    print(f"final h vs fp64: fp32 max |dh| = {float((h32 - h64).abs().max()):.3e}, "
+          f"fp16s {float((h16 - h64).abs().max()):.3e}", flush=True)
+    for n, mx, my, expect, lub, got64, got32, got16 in rows:
         # the linear eigenvalue, to 3% of the rate (plus the O(1e-3) amplitude nonlinearity)
         assert abs(got64 - expect) <= 0.03 * abs(expect) + 2e-8, (mx, my, got64, expect)
         assert abs(got32 - got64) <= 0.03 * abs(expect) + 2e-8, (mx, my, got32, got64)
+        assert abs(got16 - got64) <= 0.03 * abs(expect) + 2e-8, (mx, my, got16, got64)
     # sign structure of eq. "RTgrowth": growth below the neutral wavenumber, decay above
     kc_modes = math.sqrt(abs(p["g"]) / p["gamma"]) * N / (2 * math.pi)
-    for n, mx, my, expect, lub, got64, _ in rows:
+    for n, mx, my, expect, lub, got64, _, _ in rows:
         if n < 0.9 * kc_modes:
             assert got64 > 0, (mx, my, got64)
         if n > 1.05 * kc_modes:
