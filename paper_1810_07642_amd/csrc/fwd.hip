@@ -33,7 +33,11 @@ namespace tflbm {
 // Loads the stored deviations d_l = f_l - E_l(href) of population l at the
 // lane's columns of one row (resource `row`); oe/o16 are the lane's byte
 // offsets in a segment of the working type (FP32 or FP64) and in an FP16
-// segment; the segment offset is a compile-time immediate.
+// segment; the segment offset is a compile-time immediate.  FP16S moving
+// populations stay in their stored form, the FP16 words of the lane's two
+// columns packed in out[0] (column 0 in the low half; out[1] unused), and are
+// decoded only where the row is consumed (unpack16): a conversion here would
+// make the prefetch of a row wait for its own loads.
 template <int P>
 __device__ __forceinline__ void load_raw(rsrc_t row, int l, const int *oe, const int *o16, bool vec,
                                          typename Form<P>::T *out, const StepArgs &A) {
@@ -61,14 +65,13 @@ __device__ __forceinline__ void load_raw(rsrc_t row, int l, const int *oe, const
         for (int v = 0; v < V; ++v) out[v] = ld_f32(row, oe[v] + seg);
       }
     } else {
+      static_assert(V == 2, "FP16S packs the two columns of a lane in one word");
       if (vec) {
-        const __half2 q = ld_f16x2(row, o16[0] + seg);
-        out[0] = dec16(__low2half(q), A.qinv);
-        out[1] = dec16(__high2half(q), A.qinv);
+        out[0] = __uint_as_float(__builtin_bit_cast(unsigned int, ld_f16x2(row, o16[0] + seg)));
       } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) out[v] = dec16(ld_f16(row, o16[v] + seg), A.qinv);
+        out[0] = __uint_as_float(__builtin_bit_cast(unsigned int, __halves2half2(ld_f16(row, o16[0] + seg), ld_f16(row, o16[1] + seg))));
       }
+      out[1] = 0.0f;
     }
   }
 }
@@ -101,6 +104,61 @@ __device__ __forceinline__ void load_row(rsrc_t row, const Lane<P> &L, typename 
   } else {
 #pragma unroll
     for (int l = 0; l < 9; ++l) load_raw<P>(row, l, L.oe, L.o16, L.vec, out[l], A);
+  }
+}
+
+// FP32 rows in flight are held as one 64-bit word per population (the
+// lane's two columns, column 0 in the low half), the shape of the 8-byte
+// load: a 64-bit value keeps its aligned register pair up to the point the
+// row is consumed, so the load writes those registers directly and nothing
+// waits for it before then (held as two floats, the x shift of the consumer
+// leads the register allocator to swap the pair with moves that wait).
+__device__ __forceinline__ void load_row(rsrc_t row, const Lane<kF32> &L, unsigned long long (&out)[9]) {
+  if (L.allvec) {
+#pragma unroll
+    for (int l = 0; l < 9; ++l)
+      out[l] = __builtin_bit_cast(unsigned long long,
+                                  __builtin_amdgcn_raw_buffer_load_b64(row, L.oe[0] + seg_offset<kF32>(l), 0, kLoadPolicy));
+  } else {
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      const int seg = seg_offset<kF32>(l);
+      if (L.vec) {
+        out[l] = __builtin_bit_cast(unsigned long long, __builtin_amdgcn_raw_buffer_load_b64(row, L.oe[0] + seg, 0, kLoadPolicy));
+      } else {
+        const u32x2 w = {__builtin_amdgcn_raw_buffer_load_b32(row, L.oe[0] + seg, 0, kLoadPolicy),
+                         __builtin_amdgcn_raw_buffer_load_b32(row, L.oe[1] + seg, 0, kLoadPolicy)};
+        out[l] = __builtin_bit_cast(unsigned long long, w);
+      }
+    }
+  }
+}
+
+// Kappa at the lane's columns of one row of the kappa field (resource krow),
+// in flight as the rows are: one 64-bit word (two FP32 columns, column 0 in
+// the low half) or one FP64 value; kappa_cols splits it into columns.
+template <int P> using KapBuf = std::conditional_t<Form<P>::V == 2, unsigned long long, double>;
+template <int P> __device__ __forceinline__ void load_kappa(rsrc_t krow, const Lane<P> &L, KapBuf<P> &out) {
+  if constexpr (Form<P>::V == 2) {
+    if (L.allvecp || L.vecp) {
+      out = __builtin_bit_cast(unsigned long long, __builtin_amdgcn_raw_buffer_load_b64(krow, L.col[0] * 4, 0, kLoadPolicy));
+    } else {
+      const u32x2 w = {__builtin_amdgcn_raw_buffer_load_b32(krow, L.col[0] * 4, 0, kLoadPolicy),
+                       __builtin_amdgcn_raw_buffer_load_b32(krow, L.col[1] * 4, 0, kLoadPolicy)};
+      out = __builtin_bit_cast(unsigned long long, w);
+    }
+  } else {
+    out = ld_f64(krow, L.col[0] * 8);
+  }
+}
+template <int P>
+__device__ __forceinline__ void kappa_cols(const KapBuf<P> &k, typename Form<P>::T (&out)[Form<P>::V]) {
+  if constexpr (Form<P>::V == 2) {
+    const u32x2 w = __builtin_bit_cast(u32x2, k);
+    out[0] = __uint_as_float(w.x);
+    out[1] = __uint_as_float(w.y);
+  } else {
+    out[0] = k;
   }
 }
 
@@ -169,8 +227,9 @@ template <int P, bool KF> struct Stage {
   T kn[V], kr[V];                     // kappa of rows r and r-1
   T (*hist)[9][64 * V];
 
-  __device__ __forceinline__ void ingest(int k, int ry, const T (&f)[9][V], T (&f2)[9][V], const Lane<P> &L,
-                                         const StepArgs &A, int lane) {
+  // kap: kappa of row r (loaded with the row, load_kappa; unused without a
+  // kappa field)
+  __device__ __forceinline__ void ingest(int k, const T (&f)[9][V], const T (&kap)[V], T (&f2)[9][V], int lane) {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       T hs = f[0][v];
@@ -180,28 +239,11 @@ template <int P, bool KF> struct Stage {
     }
     h0[0] = from_left(h0[V]);
     h0[V + 1] = from_right(h0[1]);
+    // kappa of row r, used by the pressure of row r at the next row
 #pragma unroll
-    for (int v = 0; v < V; ++v) kr[v] = kn[v];
-    if constexpr (KF) {
-      // kappa of row r, used by the pressure of row r at the next row
-      const uint32_t prb = (uint32_t)(A.ldx * sizeof(T));
-      const rsrc_t krow = make_rsrc((const char *)A.kfield + (size_t)ry * prb, prb);
-      if constexpr (V == 2) {
-        if (L.allvecp) {
-          const float2 kv = ld_f32x2(krow, L.col[0] * 4);
-          kn[0] = kv.x;
-          kn[1] = kv.y;
-        } else if (L.vecp) {
-          const float2 kv = ld_f32x2(krow, L.col[0] * 4);
-          kn[0] = kv.x;
-          kn[1] = kv.y;
-        } else {
-          kn[0] = ld_f32(krow, L.col[0] * 4);
-          kn[1] = ld_f32(krow, L.col[1] * 4);
-        }
-      } else {
-        kn[0] = ld_f64(krow, L.col[0] * 8);
-      }
+    for (int v = 0; v < V; ++v) {
+      kr[v] = kn[v];
+      if constexpr (KF) kn[v] = kap[v];
     }
     // row r-2 leaves the LDS slot that row r takes over
     const int slot = k & 1;
@@ -451,38 +493,55 @@ __device__ __forceinline__ void fp16s_roundtrip(float (&post)[9][V], const float
   }
 }
 
-// FP16S decoding of stored row r (raw values: slot 0 the site's s, slots
-// l >= 1 the scaled-back FP16 differences) into deviations, per stored column:
-// moving populations add the rest equilibrium of their source row (r for
-// c_ly = 0, r - 1 for +1, r + 1 for -1); the rest deviation of row r's sites
-// is implied by their s and the moving populations they emitted, which sit in
-// rows r (c_ly = 0), r + 1 (+1) and r - 1 (-1, kept from the previous row as
-// cq together with its s, cs).
+// Scaled-back FP16 difference of column v from a word of two packed FP16
+// values (load_raw).
+__device__ __forceinline__ float unpack16(float w, int v, float qinv) {
+  const unsigned int u = __float_as_uint(w);
+  return dec16(__ushort_as_half((unsigned short)(v ? (u >> 16) : (u & 0xffffu))), qinv);
+}
+
+// FP16S decoding of stored row r (slot 0 the site's s, slots l >= 1 the
+// packed FP16 differences) into deviations, per stored column: moving
+// populations add the rest equilibrium of their source row (r for c_ly = 0,
+// r - 1 for +1, r + 1 for -1); the rest deviation of row r's sites is implied
+// by their s and the moving populations they emitted, which sit in rows r
+// (c_ly = 0), r + 1 (+1) and r - 1 (-1, kept from the previous row as cq
+// together with its s, cs).  On return cs and cq hold row r's values for the
+// next row.
 template <int V, bool G0>
-__device__ __forceinline__ void fp16s_decode(const float (&cur)[9][V], const float (&nxt)[9][V], const float (&cs)[V],
-                                             const float (&cq)[3][V], const StepArgs &A, float (&d)[9][V]) {
+__device__ __forceinline__ void fp16s_decode(const float (&cur)[9][V], const float (&nxt)[9][V], float (&cs)[V],
+                                             float (&cq)[3][V], const StepArgs &A, float (&d)[9][V]) {
   const float g16 = (float)A.g, h2 = 2.0f * (float)A.href;
 #pragma unroll
   for (int v = 0; v < V; ++v) {
-    float t[9];
+    float qc[9], qn[9], t[9];
+#pragma unroll
+    for (int l = 1; l < 9; ++l) {
+      qc[l] = unpack16(cur[l][0], v, A.qinv);
+      qn[l] = kCy[l] > 0 ? unpack16(nxt[l][0], v, A.qinv) : 0.0f;
+    }
     t[0] = 0.0f;
     if constexpr (G0) {  // g = 0: the values are the differences themselves
 #pragma unroll
       for (int l = 1; l < 9; ++l) {
-        d[l][v] = cur[l][v];
-        t[l] = kCy[l] == 0 ? cur[l][v] : (kCy[l] > 0 ? nxt[l][v] : cq[l >= 6 ? l - 6 : 0][v]);
+        d[l][v] = qc[l];
+        t[l] = kCy[l] == 0 ? qc[l] : (kCy[l] > 0 ? qn[l] : cq[l >= 6 ? l - 6 : 0][v]);
       }
     } else {
       const Rest16 em = rest16(cs[v], g16, h2), e0 = rest16(cur[0][v], g16, h2), ep = rest16(nxt[0][v], g16, h2);
 #pragma unroll
       for (int l = 1; l < 9; ++l) {
         const Rest16 &e = kCy[l] == 0 ? e0 : (kCy[l] > 0 ? em : ep);
-        d[l][v] = rest16_l(e, l) + cur[l][v];
-        const float qo = kCy[l] == 0 ? cur[l][v] : (kCy[l] > 0 ? nxt[l][v] : cq[l >= 6 ? l - 6 : 0][v]);
+        d[l][v] = rest16_l(e, l) + qc[l];
+        const float qo = kCy[l] == 0 ? qc[l] : (kCy[l] > 0 ? qn[l] : cq[l >= 6 ? l - 6 : 0][v]);
         t[l] = rest16_l(e0, l) + qo;
       }
     }
     d[0][v] = rest16_d0(cur[0][v], t);
+    cs[v] = cur[0][v];
+    cq[0][v] = qc[6];
+    cq[1][v] = qc[7];
+    cq[2][v] = qc[8];
   }
 }
 
@@ -596,7 +655,6 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   constexpr int HALO = 2 + 3 * (NS - 1);
   const int K = (yend - y0) + 2 * HALO;
   auto rsrc_src = [&](int row) { return make_rsrc(A.src + row * rowB, (uint32_t)rowB); };
-  T fa[9][V], fb[9][V];  // stored values of rows r (being consumed) and r + 1
   int ry = wrap(y0 - HALO, ny);                          // row r of stage 0
   int rpre = ry + 2 >= ny ? (ry + 2) % ny : ry + 2;      // row r + 2
   // FP16S decodes row r with rows r - 1 and r + 1 (fp16s_decode): the row
@@ -611,38 +669,59 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       cs[v] = fp[0][v];
-      cq[0][v] = fp[6][v];
-      cq[1][v] = fp[7][v];
-      cq[2][v] = fp[8][v];
+      cq[0][v] = unpack16(fp[6][0], v, A.qinv);
+      cq[1][v] = unpack16(fp[7][0], v, A.qinv);
+      cq[2][v] = unpack16(fp[8][0], v, A.qinv);
     }
   }
-  load_row<P>(rsrc_src(ry), L, fa, A);
+  // kappa travels with the rows: ka and kb hold the kappa of the rows in fa
+  // and fb, and stage 1, three rows behind stage 0, takes it from kq (the
+  // kappa of stage 0's last three rows)
+  const uint32_t kpitch = (uint32_t)(A.ldx * sizeof(T));
+  auto rsrc_kap = [&](int row) { return make_rsrc((const char *)A.kfield + (size_t)row * kpitch, kpitch); };
+  KapBuf<P> ka, kb;
+  T kq[3][V];
+  using RowBuf = std::conditional_t<P == kF32, unsigned long long[9], T[9][V]>;
+  RowBuf fa, fb;  // stored values of rows r (being consumed) and r + 1
+  auto load_buf = [&](rsrc_t row, RowBuf &out) {
+    if constexpr (P == kF32) load_row(row, L, out);
+    else load_row<P>(row, L, out, A);
+  };
+  load_buf(rsrc_src(ry), fa);
+  if constexpr (KF) load_kappa<P>(rsrc_kap(ry), L, ka);
   if (KL > 1) {
     const int r1 = ry + 1 == ny ? 0 : ry + 1;
-    load_row<P>(rsrc_src(r1), L, fb, A);
+    load_buf(rsrc_src(r1), fb);
+    if constexpr (KF) load_kappa<P>(rsrc_kap(r1), L, kb);
   }
 
-  auto iteration = [&](int k, T(&cur)[9][V], const T(&nxt)[9][V]) {
+  auto iteration = [&](int k, RowBuf &cur, const RowBuf &nxt, KapBuf<P> &kcur) {
     T f[9][V], f2[9][V];
-    if constexpr (P == kF16S) {
+    if constexpr (P == kF32) {
+#pragma unroll
+      for (int l = 0; l < 9; ++l) {
+        const u32x2 w = __builtin_bit_cast(u32x2, cur[l]);
+        const T c[2] = {__uint_as_float(w.x), __uint_as_float(w.y)};
+        shift_x<T, V>(l, c, f[l]);
+      }
+    } else if constexpr (P == kF16S) {
       T d[9][V];
       fp16s_decode<V, G0>(cur, nxt, cs, cq, A, d);
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        cs[v] = cur[0][v];
-        cq[0][v] = cur[6][v];
-        cq[1][v] = cur[7][v];
-        cq[2][v] = cur[8][v];
-      }
 #pragma unroll
       for (int l = 0; l < 9; ++l) shift_x<T, V>(l, d[l], f[l]);
     } else {
 #pragma unroll
       for (int l = 0; l < 9; ++l) shift_x<T, V>(l, cur[l], f[l]);
     }
-    S0.ingest(k, ry, f, f2, L, A, lane);
-    // prefetch row r + 2 into the registers just freed
-    if (k + 2 < KL) load_row<P>(rsrc_src(rpre), L, cur, A);
+    T k0[V];
+    if constexpr (KF) kappa_cols<P>(kcur, k0);
+    S0.ingest(k, f, k0, f2, lane);
+    // prefetch row r + 2 into the registers just freed.  Past the tile's last
+    // row the loads go to an empty buffer range (no memory access, zeros):
+    // every iteration issues the same loads, so the compiler's waits for a
+    // row need not drain the loads of the rows after it.
+    load_buf(k + 2 < KL ? rsrc_src(rpre) : make_rsrc(A.src, 0), cur);
+    if constexpr (KF) load_kappa<P>(k + 2 < KL ? rsrc_kap(rpre) : make_rsrc(A.kfield, 0), L, kcur);
     T post[9][V], hv[V], jxv[V], jyv[V];
     if (S0.finish(k, f2, post, hv, jxv, jyv, C, L, bad)) {
       const int q = y0 - HALO + k - 2;  // row of the post-collision values (unwrapped)
@@ -681,9 +760,8 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
         shift_x<T, V>(5, post[5], pendZ[2]);
         if (e >= 2) {
           const int j = e - 2;  // stage 1 row index; its row is q - 1 = y0 - 2 + j
-          const int rowB1 = wrap(y0 - 2 + j, ny);
           T g2[9][V];
-          S1.ingest(j, rowB1, g, g2, L, A, lane);
+          S1.ingest(j, g, kq[2], g2, lane);
           T post2[9][V], hv2[V], jx2[V], jy2[V];
           if (S1.finish(j, g2, post2, hv2, jx2, jy2, C, L, bad)) {
             store_row<P, G0>(A, y0 - 4 + j, post2, hv2, L, x0, xend, lane);
@@ -694,14 +772,26 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
         }
       }
     }
+    if constexpr (KF && NS == 2) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        kq[2][v] = kq[1][v];
+        kq[1][v] = kq[0][v];
+        kq[0][v] = k0[v];
+      }
+    }
     ry = ry + 1 == ny ? 0 : ry + 1;
     rpre = rpre + 1 == ny ? 0 : rpre + 1;
   };
 
-  for (int k = 0; k < K; k += 2) {
-    iteration(k, fa, fb);
-    if (k + 1 < K) iteration(k + 1, fb, fa);
+  // rows in pairs, so that each buffer keeps its registers around the loop;
+  // an odd last row after it
+  int k = 0;
+  for (; k + 1 < K; k += 2) {
+    iteration(k, fa, fb, ka);
+    iteration(k + 1, fb, fa, kb);
   }
+  if (k < K) iteration(k, fa, fb, ka);
 
   const unsigned long long m = __ballot(bad);
   if (m != 0ull && lane == __ffsll((unsigned long long)m) - 1) atomicOr(A.flag, 1);
