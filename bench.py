@@ -254,8 +254,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the thin-film step runs on a single MI355X in this build "
-              "(multi-GPU slab decomposition is described in DESIGN.md but not built)", file=sys.stderr)
+        print("bench.py measures one GPU: the thin-film step runs on a single MI355X "
+              "(the library has no multi-GPU slab decomposition)", file=sys.stderr)
         sys.exit(2)
 
     import torch
