@@ -63,7 +63,16 @@ void plan_launches(tflbm_sim *s) {
   s->rows = choose_rows(ny, s->nstrips, occ1 * cus, kMinRowsStep, "TFLBM_ROWS");
   s->ntiles = s->nstrips * ((ny + s->rows - 1) / s->rows);
   s->per_xcd = (s->ntiles + 7) / 8;
-  s->rows2 = choose_rows(ny, s->nstrips, occ2 * cus, kMinRowsStep, "TFLBM_ROWS2");
+  // The FP32 fused kernel, bound by its bytes, runs faster with chunks planned
+  // for seven resident wavefronts per CU than for the eight its resources
+  // allow (taller chunks, fewer halo rows, less contention for HBM); measured
+  // MLUPS, eight against seven: 2048^2 97.5k / 101.3k, 3072^2 107.1k / 111.2k,
+  // 4096^2 110.3k / 113.5k, 6144^2 118.1k / 118.2k, 8192^2 119.5k / 121.2k,
+  // with every chunk count in between slower than both.  FP64 and FP16S are
+  // fastest with all eight (FP16S, bound by its VALU, loses 3-7 % with
+  // taller chunks).
+  const int plan2 = s->p.prec == kF32 && occ2 > 7 ? 7 : occ2;
+  s->rows2 = choose_rows(ny, s->nstrips, plan2 * cus, kMinRowsStep, "TFLBM_ROWS2");
   s->ntiles2 = s->nstrips * ((ny + s->rows2 - 1) / s->rows2);
   s->per_xcd2 = (s->ntiles2 + 7) / 8;
   // Two fused steps per pass pay off once the one-step plan can no longer give
