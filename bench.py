@@ -32,7 +32,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
 BYTES_PER_SITE = {"fp64": 152, "fp32": 76, "fp16s": 44}  # read + write 9 populations, + kappa field
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "step_fp32_dewetting4096_traffic.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1810_07642_amd", "csrc", f) for f in ("fwd.hip", "device.h")]
+# the step kernel and the launch plan that sets its tiles (its traffic depends on both)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1810_07642_amd", "csrc", f) for f in ("fwd.hip", "device.h", "api.hip")]
 
 
 def log(*a):
@@ -40,9 +41,9 @@ def log(*a):
 
 
 def kernel_source_hash():
-    """Hash of the step kernel's source code with comments and blank lines
-    removed, so that the committed counter summary stays valid across edits
-    of comments only."""
+    """Hash of the step kernel's and its launch plan's source code with
+    comments and blank lines removed, so that the committed counter summary
+    stays valid across edits of comments only."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
         text = open(p).read()
