@@ -124,10 +124,14 @@ int tflbm_check_params(const tflbm_params *p);
  * and tflbm_step_capture), TFLBM_ADJ_FUSE=1 or 2 (the same for the reverse
  * steps of tflbm_adj_steps; by default two where the lattice is large enough
  * for it to pay), TFLBM_ROWS, TFLBM_ROWS2, TFLBM_ADJ_ROWS,
- * TFLBM_ADJ_ROWS2 (rows per chunk of the one- and two-step kernels). */
+ * TFLBM_ADJ_ROWS2 (rows per chunk of the one- and two-step kernels),
+ * TFLBM_GRAPH=0 or 1 (read at tflbm_init: whether tflbm_step replays blocks
+ * of steps from graphs; by default on lattices of at most 2^20 sites). */
 int tflbm_create(const tflbm_params *p, tflbm_sim **out);
 
-/* Releases the handle (host memory only; no device memory is owned). */
+/* Releases the handle: its host memory and, if tflbm_step captured any, its
+ * step graphs and the stream it captured them on (after waiting for the
+ * device).  No device memory is owned. */
 void tflbm_destroy(tflbm_sim *sim);
 
 /* Bytes of device workspace the handle needs: two population buffers, the
@@ -136,7 +140,8 @@ void tflbm_destroy(tflbm_sim *sim);
 size_t tflbm_workspace_bytes(const tflbm_sim *sim);
 
 /* Attaches a caller-allocated device workspace of `bytes` >= tflbm_workspace_bytes
- * bytes, 256-byte aligned.  Re-binding detaches the previous one and clears
+ * bytes, 256-byte aligned.  Re-binding detaches the previous one, releases
+ * the step graphs (which name it; after waiting for the device) and clears
  * the initialised state. */
 int tflbm_bind(tflbm_sim *sim, void *d_ws, size_t bytes);
 
@@ -145,11 +150,23 @@ int tflbm_bind(tflbm_sim *sim, void *d_ws, size_t bytes);
  * FP64, every value > 0 (checked on the device; reported by tflbm_check).
  * d_theta: [ny][nx] FP64 contact angles, or NULL for the uniform
  * params.theta0 (then the step reads no kappa field).  Sets the step count
- * to 0 and clears the status word. */
+ * to 0 and clears the status word; releases the step graphs of an earlier
+ * init (after waiting for the device). */
 int tflbm_init(tflbm_sim *sim, const double *d_h0, const double *d_theta, tflbm_stream_t stream);
 
-/* (async) Advances nsteps >= 0 time steps of eq. "LBE". */
+/* (async) Advances nsteps >= 0 time steps of eq. "LBE".  On lattices whose
+ * steps are bound by launch latency (at most 2^20 sites; TFLBM_GRAPH), whole
+ * blocks of 64 steps go out as one graph launch on `stream`: the block's
+ * kernel launches are captured on first use, once for each of the two buffer
+ * parities a block can start from, on a stream the handle creates for it.
+ * The results are the same bits as with plain launches.  Where `stream` is
+ * itself being captured, or capturing fails, the steps are launched one by
+ * one. */
 int tflbm_step(tflbm_sim *sim, int64_t nsteps, tflbm_stream_t stream);
+
+/* Number of step graphs the handle holds (0, 1 or 2: one per starting buffer
+ * parity of a block); -1 for NULL. */
+int tflbm_step_graphs(const tflbm_sim *sim);
 
 /* Number of steps taken since tflbm_init (host counter). */
 int64_t tflbm_step_count(const tflbm_sim *sim);

@@ -51,6 +51,7 @@ SIGNATURES = {
     "tflbm_init": (_int, [_vp, _dp, _dp, _vp]),
     "tflbm_step": (_int, [_vp, _i64, _vp]),
     "tflbm_step_count": (_i64, [_vp]),
+    "tflbm_step_graphs": (_int, [_vp]),
     "tflbm_read": (_int, [_vp, _dp, _dp, _dp, _vp]),
     "tflbm_mass": (_int, [_vp, ctypes.POINTER(ctypes.c_double), _vp]),
     "tflbm_check": (_int, [_vp, _vp]),

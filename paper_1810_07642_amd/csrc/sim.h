@@ -27,6 +27,11 @@ struct tflbm_sim {
   int rows2 = 0, ntiles2 = 0, per_xcd2 = 0;
   int fuse = 0;           // steps per pass: 1, 2 (when possible), 0 = 2 if fuse_fits
   bool fuse_fits = false; // the lattice is too large for one round of one-row tiles
+  // launch-bound lattices: blocks of steps replayed from captured graphs, one
+  // per starting buffer parity, captured on a stream of the library's own
+  bool graphs = false;
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
   // reverse pass
   int adj_cur = 0;        // 0: first adjoint buffer holds the current adjoint
   bool adj_seeded = false;
@@ -55,5 +60,8 @@ int choose_rows(int ny, int nstrips, int slots, int min_rows, const char *env_na
 
 // Chooses the launch shapes of the step kernels (needs the device).
 void plan_launches(tflbm_sim *s);
+
+// Releases the captured step graphs of `s`, after waiting for the device.
+void drop_graphs(tflbm_sim *s);
 
 }  // namespace tflbm

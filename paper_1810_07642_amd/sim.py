@@ -139,6 +139,12 @@ class Sim:
     def steps(self):
         return int(self.lib.tflbm_step_count(self.h))
 
+    @property
+    def step_graphs(self):
+        """Step graphs the handle holds (tflbm_step replays blocks of steps
+        from them on launch-bound lattices)."""
+        return int(self.lib.tflbm_step_graphs(self.h))
+
     def read(self, out=None):
         """(h, ux, uy) as float64 [ny, nx] tensors on the device."""
         if out is None:

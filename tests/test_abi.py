@@ -111,6 +111,7 @@ def test_call_order_and_null_pointers(lib):
     assert lib.tflbm_init(h, None, None, None) == _lib.TFLBM_EINVAL
     assert lib.tflbm_step(h, 1, None) == _lib.TFLBM_ESTATE
     assert lib.tflbm_step(h, -1, None) == _lib.TFLBM_EINVAL
+    assert lib.tflbm_step_graphs(h) == 0 and lib.tflbm_step_graphs(None) == -1
     assert lib.tflbm_read(h, None, None, None, None) == _lib.TFLBM_ESTATE
     m = ctypes.c_double()
     assert lib.tflbm_mass(h, ctypes.byref(m), None) == _lib.TFLBM_ESTATE

@@ -333,6 +333,45 @@ def test_fused_steps_equal_single_steps_bitwise(prec, href, g):
             assert torch.equal(a, b), (prec, href, ny, nx)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_graph_replayed_steps_equal_launched_steps_bitwise(prec):
+    """On launch-bound lattices tflbm_step sends whole blocks of 64 steps as
+    one graph launch, captured once per starting buffer parity.  Against the
+    same calls with graphs off: the same bits after every call of a sequence
+    whose blocks start from both parities (odd step counts between them) and
+    replay each graph several times, with eager work (mass, readout, a
+    checkpoint) between the replays; ragged and odd grids, with and without
+    a kappa field, one and two steps per pass."""
+    import os
+    from paper_1810_07642_amd import Sim
+    p = dict(tau=0.9, gamma=0.01, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5, ay=-1e-5)
+    calls = (150, 1, 129, 64, 3, 200)
+    for (ny, nx, field, fuse) in [(70, 150, True, "2"), (23, 37, False, "1"), (130, 97, True, "2")]:
+        h0, th = random_case(ny, nx, 43)
+        runs, graphs = [], []
+        for graph in ("1", "0"):
+            os.environ["TFLBM_GRAPH"] = graph
+            os.environ["TFLBM_FUSE"] = fuse
+            try:
+                sim = Sim(nx, ny, prec, **p).init(h0, th if field else None)
+            finally:
+                del os.environ["TFLBM_GRAPH"], os.environ["TFLBM_FUSE"]
+            seq = []
+            for n in calls:
+                sim.step(n)
+                sim.mass()
+                seq.append((sim.state_save().cpu(),) + tuple(t.cpu() for t in sim.read()))
+            sim.check()
+            assert sim.steps == sum(calls)
+            graphs.append(sim.step_graphs)
+            runs.append(seq)
+            del sim
+        assert graphs == [2, 0], graphs
+        for i, (a_call, b_call) in enumerate(zip(*runs)):
+            for a, b in zip(a_call, b_call):
+                assert torch.equal(a, b), (prec, ny, nx, i)
+
+
 @pytest.mark.parametrize("g", [1e-3, 0.0])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
 def test_fused_capture_equals_single_step_capture_bitwise(prec, g):
