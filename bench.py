@@ -233,7 +233,22 @@ def cpu_baseline(p, h0, th, budget_s=12.0):
     n = h0.numel()
     return {"value": n * done / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(), "kind": "oracle",
             "sample": f"{done} whole steps of the {h0.shape[1]}x{h0.shape[0]} dewetting workload, FP64, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """CPU model and logical CPU count of the host the oracle ran on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "os_cpu_count": os.cpu_count()}
 
 
 def main():
