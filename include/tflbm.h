@@ -156,9 +156,10 @@ int tflbm_init(tflbm_sim *sim, const double *d_h0, const double *d_theta, tflbm_
 
 /* (async) Advances nsteps >= 0 time steps of eq. "LBE".  On lattices whose
  * steps are bound by launch latency (at most 2^20 sites; TFLBM_GRAPH), whole
- * blocks of 64 steps go out as one graph launch on `stream`: the block's
- * kernel launches are captured on first use, once for each of the two buffer
- * parities a block can start from, on a stream the handle creates for it.
+ * blocks of 64 steps go out as one graph launch on `stream` once the handle
+ * has run 256 steps: the block's kernel launches are captured on first use,
+ * once for each of the two buffer parities a block can start from, on a
+ * stream the handle creates for it.
  * The results are the same bits as with plain launches.  Where `stream` is
  * itself being captured, or capturing fails, the steps are launched one by
  * one. */
