@@ -185,9 +185,10 @@ def fp64_by_lattice(mlups_4096):
     out = {}
     for n, steps in ((128, 2000), (256, 2000), (512, 1000), (1024, 500), (2048, 200)):
         p, h0, th = inputs.patterned_dewetting(n=n)
-        # the warm-up covers a whole block of steps, so that the step graph of
-        # a launch-bound lattice is captured before the timed steps
-        ms, _, _ = run_form("fp64", p, h0, th, steps, 128)
+        # the warm-up runs past the point (256 steps) from which a handle on a
+        # launch-bound lattice captures its step graph, so that the capture is
+        # not timed
+        ms, _, _ = run_form("fp64", p, h0, th, steps, 512)
         out[str(n)] = round(n * n * steps / (ms * 1e-3) / 1e6, 1)
     out["4096"] = round(mlups_4096, 1)
     return out
