@@ -23,11 +23,13 @@
  * Conventions common to every call:
  *  - All arrays passed in or out are row-major [ny][nx], x fastest, FP64,
  *    dense (row pitch nx), in HIP device memory unless a pointer is named h_*.
- *  - The library never allocates device memory.  The caller allocates the
- *    workspace (tflbm_workspace_bytes), the adjoint workspace
+ *  - The library never allocates device memory for data.  The caller
+ *    allocates the workspace (tflbm_workspace_bytes), the adjoint workspace
  *    (tflbm_adj_bytes), checkpoints (tflbm_state_bytes) and captures
  *    (tflbm_capture_bytes), keeps them alive until the stream work that uses
- *    them has completed, and frees them.  The handle owns host memory only.
+ *    them has completed, and frees them.  The handle owns host memory and, on
+ *    launch-bound lattices, up to two step graphs and the stream they were
+ *    captured on (tflbm_step), released by tflbm_destroy.
  *  - Calls marked (async) enqueue work on `stream` and return at once;
  *    errors of already-launched kernels surface at the next blocking call.
  *    Calls marked (blocking) synchronise `stream`.
