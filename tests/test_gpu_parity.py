@@ -374,6 +374,36 @@ def test_graph_replayed_steps_equal_launched_steps_bitwise(prec):
                 assert torch.equal(a, b), (prec, ny, nx, i)
 
 
+def test_steps_captured_into_a_callers_graph():
+    """A caller may capture tflbm_step into a graph of its own
+    (torch.cuda.graph): the library then launches kernel by kernel into the
+    caller's capture instead of replaying its own step graphs, and each replay
+    of the caller's graph advances the state exactly like eager steps (three
+    replays, eager work between them)."""
+    from paper_1810_07642_amd import Sim
+    p = dict(tau=0.9, gamma=0.01, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5)
+    h0, th = random_case(70, 150, 44)
+    a = Sim(150, 70, "fp32", **p).init(h0, th)
+    b = Sim(150, 70, "fp32", **p).init(h0, th)
+    a.step(320)  # the block from step 256 on replays a captured graph
+    b.step(320)
+    assert a.step_graphs >= 1
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            a.step(128)  # an even number of buffer swaps: the replay keeps the parity
+    torch.cuda.synchronize()
+    for _ in range(3):
+        graph.replay()
+        b.step(128)
+        torch.cuda.synchronize()
+        assert torch.equal(a.state_save(), b.state_save())
+        assert b.mass() == a.mass()
+    a.check()
+
+
 @pytest.mark.parametrize("g", [1e-3, 0.0])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
 def test_fused_capture_equals_single_step_capture_bitwise(prec, g):
