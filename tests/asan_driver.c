@@ -31,10 +31,12 @@ int main(void) {
     EXPECT(tflbm_adj_steps(s, fake, fake, 3, NULL) == TFLBM_ESTATE);
     EXPECT(tflbm_adj_steps(s, fake, fake, -1, NULL) == TFLBM_EINVAL);
     EXPECT(tflbm_step_count(s) == 0);
+    EXPECT(tflbm_step_graphs(s) == 0);
     EXPECT(strlen(tflbm_strerror(TFLBM_ESTATE)) > 0 && strlen(tflbm_last_error(s)) == 0);
     tflbm_destroy(s);
   }
   EXPECT(tflbm_create(NULL, NULL) == TFLBM_EINVAL);
+  EXPECT(tflbm_step_graphs(NULL) == -1);
   tflbm_destroy(NULL);
   printf("%s (%d failures)\n", fails ? "FAILED" : "ok", fails);
   return fails != 0;
