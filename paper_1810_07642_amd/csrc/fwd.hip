@@ -363,6 +363,19 @@ template <int P, bool KF> struct Stage {
   }
 };
 
+// Two values scaled by 2^s and rounded to FP16 (round to nearest even), packed
+// in one word, the first in the low half: the stored form of a lane's two
+// columns.  The scale is a power of two, so the product is exact and the one
+// rounding is the conversion's (the same bits as __float2half_rn of the
+// product, which the round trip of the fused pass uses).
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned int enc16x2(float a, float b, float qscale) {
+  f16x2_t w;
+  w.x = (_Float16)(a * qscale);
+  w.y = (_Float16)(b * qscale);
+  return __builtin_bit_cast(unsigned int, w);
+}
+
 // Stores the post-collision deviations of row y (values at the lane's own
 // columns, hv = dh of the row) into stored column x of rows y + c_ly.
 template <int P, bool G0 = false>
@@ -381,29 +394,28 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
   const bool pair = L.pair;
   if constexpr (P == kF16S) {
     // the site's height deviation s, and each moving population as its FP16
-    // difference from the rest equilibrium e_l(s) of this (its source) site
+    // difference from the rest equilibrium e_l(s) of this (its source) site,
+    // the lane's two columns packed in one word (column 0 in the low half)
+    static_assert(V == 2, "FP16S packs the two columns of a lane in one word");
     float rest[V];
-    __half q[9][V];
+    unsigned int qw[9];
     const float g16 = (float)A.g, h2 = 2.0f * (float)A.href;
 #pragma unroll
     for (int v = 0; v < V; ++v) rest[v] = hv[v];
     if constexpr (G0) {  // g = 0: the rest equilibrium has no moving part
 #pragma unroll
-      for (int v = 0; v < V; ++v)
-#pragma unroll
-        for (int l = 1; l < 9; ++l) q[l][v] = __float2half_rn(post[l][v] * A.qscale);
+      for (int l = 1; l < 9; ++l) qw[l] = enc16x2(post[l][0], post[l][1], A.qscale);
     } else {
+      const Rest16 e0 = rest16(hv[0], g16, h2), e1 = rest16(hv[1], g16, h2);
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const Rest16 e = rest16(hv[v], g16, h2);
-#pragma unroll
-        for (int l = 1; l < 9; ++l) q[l][v] = __float2half_rn((post[l][v] - rest16_l(e, l)) * A.qscale);
-      }
+      for (int l = 1; l < 9; ++l)
+        qw[l] = enc16x2(post[l][0] - rest16_l(e0, l), post[l][1] - rest16_l(e1, l), A.qscale);
     }
     if (L.fast_store) {
       if (pair) {
 #pragma unroll
-        for (int l = 1; l < 9; ++l) st_f16x2(rowD[kCy[l] + 1], L.o16[0] + seg_offset<P>(l), q[l][0], q[l][1]);
+        for (int l = 1; l < 9; ++l)
+          __builtin_amdgcn_raw_buffer_store_b32(qw[l], rowD[kCy[l] + 1], L.o16[0] + seg_offset<P>(l), 0, kStorePolicy);
         st_f32x2(rowD[1], L.oe[0], rest[0], rest[1]);
       }
     } else {
@@ -412,11 +424,11 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
         const rsrc_t rd = rowD[kCy[l] + 1];
         const int seg = seg_offset<P>(l);
         if (pair) {
-          st_f16x2(rd, L.o16[0] + seg, q[l][0], q[l][1]);
+          __builtin_amdgcn_raw_buffer_store_b32(qw[l], rd, L.o16[0] + seg, 0, kStorePolicy);
         } else {
 #pragma unroll
           for (int v = 0; v < V; ++v)
-            if (L.out[v]) st_f16(rd, L.o16[v] + seg, q[l][v]);
+            if (L.out[v]) st_f16(rd, L.o16[v] + seg, __ushort_as_half((unsigned short)(v ? qw[l] >> 16 : qw[l] & 0xffffu)));
         }
       }
       if (pair) {
@@ -506,18 +518,20 @@ __device__ __forceinline__ float unpack16(float w, int v, float qinv) {
 // r - 1 for +1, r + 1 for -1); the rest deviation of row r's sites is implied
 // by their s and the moving populations they emitted, which sit in rows r
 // (c_ly = 0), r + 1 (+1) and r - 1 (-1, kept from the previous row as cq
-// together with its s, cs).  On return cs and cq hold row r's values for the
-// next row.
+// together with its s, cs).  The c_ly = +1 values of row r were decoded for
+// the previous row and come in cn.  On return cs, cq and cn hold the values
+// the next row needs.
 template <int V, bool G0>
 __device__ __forceinline__ void fp16s_decode(const float (&cur)[9][V], const float (&nxt)[9][V], float (&cs)[V],
-                                             float (&cq)[3][V], const StepArgs &A, float (&d)[9][V]) {
+                                             float (&cq)[3][V], float (&cn)[3][V], const StepArgs &A,
+                                             float (&d)[9][V]) {
   const float g16 = (float)A.g, h2 = 2.0f * (float)A.href;
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     float qc[9], qn[9], t[9];
 #pragma unroll
     for (int l = 1; l < 9; ++l) {
-      qc[l] = unpack16(cur[l][0], v, A.qinv);
+      qc[l] = kCy[l] > 0 ? cn[l - 2][v] : unpack16(cur[l][0], v, A.qinv);
       qn[l] = kCy[l] > 0 ? unpack16(nxt[l][0], v, A.qinv) : 0.0f;
     }
     t[0] = 0.0f;
@@ -542,6 +556,9 @@ __device__ __forceinline__ void fp16s_decode(const float (&cur)[9][V], const flo
     cq[0][v] = qc[6];
     cq[1][v] = qc[7];
     cq[2][v] = qc[8];
+    cn[0][v] = qn[2];
+    cn[1][v] = qn[3];
+    cn[2][v] = qn[4];
   }
 }
 
@@ -660,7 +677,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   // FP16S decodes row r with rows r - 1 and r + 1 (fp16s_decode): the row
   // above the first is read for its s and q_6..q_8, and one row past the
   // last (KL = K + 1 rows are loaded after it)
-  T cs[V], cq[3][V];
+  T cs[V], cq[3][V], cn[3][V];
   constexpr int KX = P == kF16S ? 1 : 0;
   const int KL = K + KX;
   if constexpr (P == kF16S) {
@@ -694,6 +711,14 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
     load_buf(rsrc_src(r1), fb);
     if constexpr (KF) load_kappa<P>(rsrc_kap(r1), L, kb);
   }
+  if constexpr (P == kF16S) {
+    // the c_ly = +1 values of the first row, which fp16s_decode otherwise
+    // carries over from the row before
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) cn[i][v] = unpack16(fa[2 + i][0], v, A.qinv);
+  }
 
   auto iteration = [&](int k, RowBuf &cur, const RowBuf &nxt, KapBuf<P> &kcur) {
     T f[9][V], f2[9][V];
@@ -706,7 +731,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
       }
     } else if constexpr (P == kF16S) {
       T d[9][V];
-      fp16s_decode<V, G0>(cur, nxt, cs, cq, A, d);
+      fp16s_decode<V, G0>(cur, nxt, cs, cq, cn, A, d);
 #pragma unroll
       for (int l = 0; l < 9; ++l) shift_x<T, V>(l, d[l], f[l]);
     } else {
