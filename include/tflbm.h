@@ -23,7 +23,9 @@
  * Conventions common to every call:
  *  - All arrays passed in or out are row-major [ny][nx], x fastest, FP64,
  *    dense (row pitch nx), in HIP device memory unless a pointer is named h_*.
- *  - The library never allocates device memory for data.  The caller
+ *  - The library never allocates device memory for data (its only device
+ *    memory of its own is the 8 KiB static reduction scratch per GPU of
+ *    tflbm_mass_noalloc).  The caller
  *    allocates the workspace (tflbm_workspace_bytes), the adjoint workspace
  *    (tflbm_adj_bytes), checkpoints (tflbm_state_bytes) and captures
  *    (tflbm_capture_bytes), keeps them alive until the stream work that uses
@@ -183,6 +185,20 @@ int tflbm_read(const tflbm_sim *sim, double *d_h, double *d_ux, double *d_uy, tf
  * reduction) into *h_mass (host memory).  The method conserves it exactly in
  * real arithmetic (Sec. III B). */
 int tflbm_mass(const tflbm_sim *sim, double *h_mass, tflbm_stream_t stream);
+
+/* (async) For callers that cannot allocate device memory or synchronise (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the total mass of tflbm_mass, same deterministic two-pass FP64
+ * reduction and same bits, written to device memory *d_mass (one double,
+ * caller-owned) without synchronising.  Its 1024 partial sums live in a
+ * static device array of the library (8 KiB per GPU, held until the process
+ * ends; the partial count does not depend on the lattice, so every lattice
+ * fits) instead of the workspace; no call allocates or frees anything.  Every
+ * call on one GPU shares that array, and the previous call's partials are
+ * overwritten: calls that overlap on one GPU (several streams, handles or
+ * threads) race and must be serialised by the caller.  TFLBM_ESTATE before
+ * tflbm_init, TFLBM_EINVAL for NULL pointers. */
+int tflbm_mass_noalloc(const tflbm_sim *sim, double *d_mass, tflbm_stream_t stream);
 
 /* (blocking) TFLBM_OK, or TFLBM_ENONFINITE if a step since tflbm_init met
  * h <= 0 or a non-finite h at an updated site, or if h0 had such a value. */

@@ -54,6 +54,7 @@ SIGNATURES = {
     "tflbm_step_graphs": (_int, [_vp]),
     "tflbm_read": (_int, [_vp, _dp, _dp, _dp, _vp]),
     "tflbm_mass": (_int, [_vp, ctypes.POINTER(ctypes.c_double), _vp]),
+    "tflbm_mass_noalloc": (_int, [_vp, _dp, _vp]),
     "tflbm_check": (_int, [_vp, _vp]),
     "tflbm_term_norms": (_int, [_vp, ctypes.POINTER(ctypes.c_double), _vp]),
     "tflbm_state_bytes": (_sz, [_vp]),

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libtflbm.so")
-SOURCES = ["api.hip", "fwd.hip", "adj.hip", "diag.hip"]
+SOURCES = ["api.hip", "fwd.hip", "adj.hip", "diag.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -293,11 +293,15 @@ int tflbm_init(tflbm_sim *sim, const double *d_h0, const double *d_theta, tflbm_
   if (!sim->ws) return TFLBM_ESTATE;
   hipStream_t st = (hipStream_t)stream;
   drop_graphs(sim);
+  // set-up of tflbm_mass_noalloc: the address of the static scratch on this device
+  double *scr = nullptr;
+  int rc = scratch_on_current_device(sim, &scr);
+  if (rc) return rc;
   sim->cur = 1;  // init writes into the "dst" of a cur=1 state, i.e. buffer A
   sim->kfield = d_theta != nullptr;
   plan_launches(sim);
   StepArgs A = make_step_args(sim);
-  int rc = hip_status(sim, hipMemsetAsync(sim->ws + sim->off_flag, 0, 256, st));
+  rc = hip_status(sim, hipMemsetAsync(sim->ws + sim->off_flag, 0, 256, st));
   if (rc) return rc;
   rc = hip_status(sim, launch_init(sim->p.prec, A, d_h0, d_theta, sim->kconst, st));
   if (rc) return rc;

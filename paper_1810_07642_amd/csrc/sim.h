@@ -64,4 +64,8 @@ void plan_launches(tflbm_sim *s);
 // Releases the captured step graphs of `s`, after waiting for the device.
 void drop_graphs(tflbm_sim *s);
 
+// Device address of the library's static reduction scratch on the current
+// device (tflbm_mass_noalloc), looked up once per device.
+int scratch_on_current_device(const tflbm_sim *s, double **out);
+
 }  // namespace tflbm

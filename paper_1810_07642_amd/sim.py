@@ -168,6 +168,16 @@ class Sim:
         self._chk(self.lib.tflbm_mass(self.h, ctypes.byref(m), self.stream), "tflbm_mass")
         return m.value
 
+    def mass_noalloc(self, out=None):
+        """Total mass as a float64 device tensor of one element, by the
+        allocation-free entry point (tflbm_mass_noalloc: partials in the
+        library's static scratch, no synchronisation)."""
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.device)
+        _buf(out, 8, self.device, "mass output")
+        self._chk(self.lib.tflbm_mass_noalloc(self.h, _addr(out), self.stream), "tflbm_mass_noalloc")
+        return out
+
     def check(self):
         """Raises TFLBMError(TFLBM_ENONFINITE) if a step met h <= 0 or non-finite h."""
         self._chk(self.lib.tflbm_check(self.h, self.stream), "tflbm_check")
