@@ -2,27 +2,30 @@
 """Throughput of the thin-film lattice Boltzmann step on one MI355X.
 
 Workload (the headline configuration): patterned-substrate dewetting on a
-4096 x 4096 periodic lattice, FP32 population storage, contact-angle stripes
-of period 256 alternating pi/9 and pi/4 (sine-smoothed edges, width 8), flat
-film h0 = 0.1 + 1e-4 U(-1, 1) (seed 2), h_* = 0.09, gamma = 0.01, tau = 1,
-delta = 1.  A "step" is one lattice time step of the whole grid; the library
+4096 x 4096 periodic lattice, contact-angle stripes of period 256 alternating
+pi/9 and pi/4 (sine-smoothed edges, width 8), flat film h0 = 0.1 + 1e-4
+U(-1, 1) (seed 2), h_* = 0.09, gamma = 0.01, tau = 1, delta = 1.  The headline
+value is the FP64 step, the arithmetic of the paper's own benchmark table
+(Sec. IV).  A "step" is one lattice time step of the whole grid; the library
 runs two steps per launch of its fused step kernel (the intermediate state
-stays on chip); MLUPS = nx ny steps / (t 1e6) (Sec. IV of the paper).
+stays on chip); MLUPS = nx ny steps / (t 1e6) (Sec. IV).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Prints one JSON line.  Besides the headline FP32 number it reports the FP64
-and FP16-shifted forms, their errors against the FP64 path, the FP32/FP64
-speed-up, the adjoint/forward time ratio of the inverse-design case
-(512 x 512, 4096 steps, checkpoints every 64), the roofline position of the
-step kernel and the FP64 CPU oracle timed on a bounded sample.
+Prints one JSON line.  Besides the headline it reports, per storage form
+(FP64, FP32, FP16-shifted) and for the two-step reverse pass, the roofline
+position of the dominant kernel per pass (the bytes one launch must move over
+its launch time, against the 8 TB/s HBM peak and against the record-copy
+ceiling measured in the same run); the errors of the FP32 and FP16S forms
+against the FP64 path after a fixed 2000 steps; the FP32/FP64 speed-up; the
+adjoint/forward time ratio of the inverse-design case (512 x 512, 4096 steps,
+checkpoints every 64) with the FP32-forward gradient error; and the FP64 CPU
+oracle timed on a bounded sample.
 """
 import argparse
-import hashlib
 import json
 import math
 import os
-import re
 import sys
 import time
 
@@ -30,53 +33,59 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
-BYTES_PER_SITE = {"fp64": 152, "fp32": 76, "fp16s": 44}  # read + write 9 populations, + kappa field
-PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "step_fp32_dewetting4096_traffic.md")
-# the step kernel and the launch plan that sets its tiles (its traffic depends on both)
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1810_07642_amd", "csrc", f) for f in ("fwd.hip", "device.h", "api.hip")]
+# Algorithmic bytes per site of one pass of the fused step kernel: read and
+# write each of the 9 populations once, plus the kappa field read once.
+BYTES_PER_SITE = {"fp64": 152, "fp32": 76, "fp16s": 44}
+HREF = {"fp64": 0.0, "fp32": 0.1, "fp16s": 0.1}  # storage reference height: the film's mean
+# Reverse pass, two steps per launch, FP32 adjoint with FP64 kappa gradient:
+# adjoint read and write 36 + 36, two captures 24, kappa 4, g_kappa RMW 16.
+ADJ2_BYTES_PER_SITE = 116
+PROFILES = os.path.join(ROOT, "profiles")
+EXTRA_STEPS = 400   # timed steps of each form in the per-form table (independent of --steps)
+ACCURACY_STEPS = 2000  # fixed horizon of the accuracy legs
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    """Hash of the step kernel's and its launch plan's source code with
-    comments and blank lines removed, so that the committed counter summary
-    stays valid across edits of comments only."""
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        text = open(p).read()
-        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        for line in text.splitlines():
-            code = line.split("//", 1)[0].rstrip()
-            if code:
-                h.update(code.encode() + b"\n")
-    return h.hexdigest()[:16]
+def profile_path(form):
+    return os.path.join(PROFILES, f"step_{form}_dewetting4096_traffic.md")
 
 
-def committed_traffic():
-    """(HBM bytes per step-kernel launch, time steps per launch) from the
-    committed rocprofv3 counter summary, if it was taken on the current kernel
-    source; else None."""
-    if not os.path.exists(PROFILE_SUMMARY):
-        return None
-    text = open(PROFILE_SUMMARY).read()
-    m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
-    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    m_steps = re.search(r"steps_per_launch:\s*([0-9]+)", text)
-    if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
-        return None
-    return float(m_val.group(1)), int(m_steps.group(1)) if m_steps else 1
+ADJ_PROFILE = os.path.join(PROFILES, "adj_step2_fp32_dewetting4096.md")
+
+
+def committed_traffic(form):
+    """(HBM bytes per launch, steps per launch) from the committed counter
+    summary of the form's step kernel, if it was taken on the current kernel
+    and launch-plan source; else None."""
+    from paper_1810_07642_amd import profiling
+    r = profiling.read_summary(profile_path(form), profiling.STEP_SOURCES)
+    return None if r is None else r[:2]
+
+
+def committed_adj_traffic():
+    from paper_1810_07642_amd import profiling
+    r = profiling.read_summary(ADJ_PROFILE, profiling.ADJ_SOURCES)
+    return None if r is None else r[:2]
+
+
+def cuda_timer():
+    """Start/stop events on the stream the library launches on (torch's
+    current stream, which Sim hands to every C-ABI call)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    return stream, e0, e1
 
 
 def timed_steps(sim, steps, warmup):
     import torch
     sim.step(warmup)
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    stream, e0, e1 = cuda_timer()
     e0.record(stream)
     sim.step(steps)
     e1.record(stream)
@@ -84,40 +93,134 @@ def timed_steps(sim, steps, warmup):
     return e0.elapsed_time(e1)  # ms
 
 
-def run_form(prec, p, h0, th, steps, warmup, fuse=None, href=0.0):
+def make_sim(prec, p, h0, th, fuse=None, href=None):
     from paper_1810_07642_amd import Sim
-    import torch
     n = h0.shape[0]
     if fuse is not None:
         os.environ["TFLBM_FUSE"] = str(fuse)
     try:
-        sim = Sim(n, n, prec, href=href, **p).init(h0, th)
+        return Sim(n, n, prec, href=HREF[prec] if href is None else href, **p).init(h0, th)
     finally:
         os.environ.pop("TFLBM_FUSE", None)
+
+
+def run_form(prec, p, h0, th, steps, warmup, fuse=None, href=None):
+    import torch
+    sim = make_sim(prec, p, h0, th, fuse, href)
     ms = timed_steps(sim, steps, warmup)
     sim.check()
-    h = sim.height()
-    mass = sim.mass()
     del sim
     torch.cuda.empty_cache()
-    return ms, h, mass
+    return ms
 
 
-def adjoint_ratio(prec="fp32", n=512, steps=4096, K=64):
+def launches(steps):
+    """Launches of the step kernel for `steps` steps on a lattice that runs
+    fused pairs (an odd count ends with one single step)."""
+    return steps // 2 + steps % 2
+
+
+def roofline_block(kernel, bytes_per_launch, launch_ms, traffic, ceiling_gbs, steps_per_launch=2):
+    """Roofline position of one kernel: its algorithmic bytes per launch over
+    its launch time, against the HBM peak (frac) and the record-copy ceiling;
+    `traffic` = (measured HBM bytes per launch, steps per launch) from the
+    committed counter summary, or None."""
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    blk = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": None if traffic is None else round(traffic[0] / (launch_ms * 1e-3) / 1e9, 1),
+           "kernel": kernel, "bytes_per_launch": int(bytes_per_launch), "steps_per_launch": steps_per_launch,
+           "launch_us": round(launch_ms * 1e3, 2)}
+    if traffic is not None:
+        blk["traffic_over_algorithmic"] = round(traffic[0] / bytes_per_launch, 4)
+    if ceiling_gbs:
+        blk["ceiling"] = {"GBps": round(ceiling_gbs, 1), "what": "record copy (tflbm_state_save) of the same buffer",
+                          "frac_of_ceiling": round(achieved / ceiling_gbs, 4)}
+    return blk
+
+
+def copy_ceiling(p, h0, th, reps=20):
+    """The library's record-copy kernel (tflbm_state_save: one read and one
+    write of every byte of a population buffer) on the FP64 state of the
+    benchmark lattice, and the runtime's device copy of the same bytes:
+    GB/s counting bytes read + written."""
+    import torch
+    sim = make_sim("fp64", p, h0, th)
+    nbytes = sim.state_bytes()
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        sim.state_save(dst)
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    stream, e0, e1 = cuda_timer()
+    e0.record(stream)
+    for _ in range(reps):
+        sim.state_save(dst)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_rec = e0.elapsed_time(e1) / reps
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_rt = e0.elapsed_time(e1) / reps
+    del sim, dst, src
+    torch.cuda.empty_cache()
+    return {"record_copy_GBps": round(2 * nbytes / (t_rec * 1e-3) / 1e9, 1),
+            "runtime_copy_GBps": round(2 * nbytes / (t_rt * 1e-3) / 1e9, 1), "bytes_copied": nbytes}
+
+
+def steady_sims(p, h0, th, steps=ACCURACY_STEPS, forms=("fp64", "fp32", "fp32_href0", "fp16s")):
+    """Handles of each form advanced `steps` untimed steps from the flat film,
+    and the accuracy of the FP32 and FP16S forms against the FP64 path there
+    (max |dh| / max h) with the mass drift of each form.  Timing starts from
+    these states: over its first ~60 steps from the flat initial film the step
+    runs up to 15 % slower per launch than later in the run (measured at
+    4096^2 FP64: 595-675 us per launch, against 577-590 us after 2000 steps),
+    and the paper's MLUPS are averages over 10^5 steps."""
+    import torch
+    sims, acc = {}, {"steps": steps, "mass_rel_drift": {}}
+    ref = None
+    for key in forms:
+        prec = "fp32" if key == "fp32_href0" else key
+        sim = make_sim(prec, p, h0, th, href=0.0 if key == "fp32_href0" else None)
+        m0 = sim.mass()
+        sim.step(steps)
+        sim.check()
+        h = sim.height()
+        acc["mass_rel_drift"][key] = (sim.mass() - m0) / m0
+        if key == "fp64":
+            ref = h
+        else:
+            acc[f"{key}_max_rel_dh_vs_fp64"] = float((h - ref).abs().max()) / float(ref.abs().max())
+        del h
+        if key == "fp32_href0":
+            del sim
+        else:
+            sims[key] = sim
+    del ref
+    torch.cuda.empty_cache()
+    return sims, acc
+
+
+def inverse_design_case(prec="fp32", n=512, steps=4096, K=64, reps=2):
     """Backward (recompute + adjoint) over forward (with checkpoints) wall time
-    of the inverse-design case; with K = 0 the forward writes every step's
-    capture and the backward is the reverse pass alone."""
+    of the inverse-design case, and the gradients of the last repetition; with
+    K = 0 the forward writes every step's capture and the backward is the
+    reverse pass alone."""
     import torch
     from paper_1810_07642_amd import TFLBMRun, inputs
     p, h0, th, target = inputs.inverse_design(n=n)
     tgt = target.cuda()
     res = []
-    for _ in range(2):  # first pass warms up
+    for _ in range(reps):  # the first pass warms up
         h0c = h0.cuda().requires_grad_(True)
         thc = th.cuda().requires_grad_(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        h = TFLBMRun.apply(h0c, thc, p, steps, K, prec)
+        h = TFLBMRun.apply(h0c, thc, dict(p, href=HREF[prec]), steps, K, prec)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         loss = 0.5 * ((h - tgt) ** 2).sum()
@@ -126,24 +229,23 @@ def adjoint_ratio(prec="fp32", n=512, steps=4096, K=64):
         t2 = time.perf_counter()
         res.append((t1 - t0, t2 - t1))
     fwd, bwd = res[-1]
-    return {"forward_s": fwd, "backward_s": bwd, "ratio": bwd / fwd, "grid": n, "steps": steps,
-            "checkpoint_every": K, "storage": prec}
+    info = {"forward_s": round(fwd, 5), "backward_s": round(bwd, 5), "ratio": round(bwd / fwd, 4), "grid": n,
+            "steps": steps, "checkpoint_every": K, "storage": prec, "href": HREF[prec]}
+    return info, (h0c.grad.detach(), thc.grad.detach())
 
 
-def reverse_sweep_at(n, K=16):
+def reverse_sweep_at(n, ceiling_gbs, K=16):
     """Per-step times of the pieces of the backward pass at n x n (the dewetting
     recipe, FP32): forward step, recompute with capture, and the adjoint, both
     two steps per pass (tflbm_adj_steps, what the backward pass runs) and one
     step per pass (tflbm_adj_step); the backward/forward ratio they give
-    (checkpoint copies excluded).  Algorithmic bytes per site and step: 104
-    one step per pass (adjoint read and write 36 + 36, h and j 12, kappa 4,
-    FP64 g_kappa read and write 16), 58 two steps per pass (116 per pass:
-    two captures, one adjoint read and write, one g_kappa update)."""
+    (checkpoint copies excluded), and the roofline block of the two-step
+    reverse kernel (116 B per site and pass)."""
     import ctypes
     import torch
     from paper_1810_07642_amd import Sim, inputs
     p, h0, th = inputs.patterned_dewetting(n=n)
-    sim = Sim(n, n, "fp32", href=0.1, **p).init(h0, th)
+    sim = Sim(n, n, "fp32", href=HREF["fp32"], **p).init(h0, th)
     cb = sim.capture_bytes()
     cap = torch.empty(K * cb, dtype=torch.uint8, device="cuda")
     adj = torch.zeros(sim.adj_bytes(), dtype=torch.uint8, device="cuda")
@@ -152,10 +254,10 @@ def reverse_sweep_at(n, K=16):
     def timed(fn):
         fn()
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
+        stream, e0, e1 = cuda_timer()
+        e0.record(stream)
         fn()
-        e1.record()
+        e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / K
 
@@ -172,10 +274,10 @@ def reverse_sweep_at(n, K=16):
     torch.cuda.empty_cache()
     return {"grid": n, "forward_us_per_step": round(f * 1e3, 1), "capture_us_per_step": round(c * 1e3, 1),
             "adjoint_us_per_step": round(a2 * 1e3, 1), "ratio": round((c + a2) / f, 3),
-            "adjoint_GBps_at_58B_per_site": round(58 * n * n / (a2 * 1e-3) / 1e9, 1),
             "adjoint_one_step_per_pass_us_per_step": round(a1 * 1e3, 1),
             "ratio_one_step_per_pass": round((c + a1) / f, 3),
-            "adjoint_one_step_per_pass_GBps_at_104B_per_site": round(104 * n * n / (a1 * 1e-3) / 1e9, 1)}
+            "roofline": roofline_block("adj_step2_kernel<float, kappa field> (two reverse steps per launch)",
+                                       ADJ2_BYTES_PER_SITE * n * n, 2 * a2, committed_adj_traffic(), ceiling_gbs)}
 
 
 def fp64_by_lattice(mlups_4096):
@@ -188,7 +290,7 @@ def fp64_by_lattice(mlups_4096):
         # the warm-up runs past the point (256 steps) from which a handle on a
         # launch-bound lattice captures its step graph, so that the capture is
         # not timed
-        ms, _, _ = run_form("fp64", p, h0, th, steps, 512)
+        ms = run_form("fp64", p, h0, th, steps, 512)
         out[str(n)] = round(n * n * steps / (ms * 1e-3) / 1e6, 1)
     out["4096"] = round(mlups_4096, 1)
     return out
@@ -254,6 +356,34 @@ def host_cpu():
     return {"model": model, "os_cpu_count": os.cpu_count()}
 
 
+def profile_run(args, p, h0, th):
+    """Short runs for rocprofv3: N steps of one form (and a record copy of its
+    state), or a reverse pass over N captured FP32 steps; then a 1 GiB runtime
+    copy that calibrates the HBM counters."""
+    import torch
+    n = args.n
+    prec = "fp32" if args.profile_adjoint else args.profile_storage
+    sim = make_sim(prec, p, h0, th)
+    if args.profile_adjoint:
+        k = args.profile_adjoint
+        cap = torch.empty(k * sim.capture_bytes(), dtype=torch.uint8, device="cuda")
+        adj = torch.empty(sim.adj_bytes(), dtype=torch.uint8, device="cuda")
+        sim.step_capture(k, cap)
+        sim.adj_seed(adj, torch.zeros(n, n, dtype=torch.float64))
+        sim.adj_steps(adj, cap, k)
+    else:
+        sim.step(args.profile_steps)
+        sim.state_save()
+    torch.cuda.synchronize()
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    what = f"reverse pass over {args.profile_adjoint} captured" if args.profile_adjoint else f"{args.profile_steps}"
+    log(f"profile run: {what} {prec} steps at {n}^2 and a 1 GiB copy")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,14 +391,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=4096, help="lattice side (default 4096)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="headline FP32 number only")
+    ap.add_argument("--no-extras", action="store_true", help="headline FP64 number and its roofline only")
     ap.add_argument("--profile-steps", type=int, default=0,
-                    help="run this many FP32 steps and a 1 GiB device copy (for rocprofv3), then exit")
+                    help="run this many steps, a record copy and a 1 GiB device copy (for rocprofv3), then exit")
     ap.add_argument("--profile-adjoint", type=int, default=0,
                     help="run the reverse pass over this many captured FP32 steps and a 1 GiB device copy "
                          "(for rocprofv3), then exit")
-    ap.add_argument("--profile-storage", default="fp32", choices=("fp64", "fp32", "fp16s"),
-                    help="storage form of the --profile-steps run (default fp32)")
+    ap.add_argument("--profile-storage", default="fp64", choices=("fp64", "fp32", "fp16s"),
+                    help="storage form of the --profile-steps run (default fp64)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -278,41 +408,37 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1810_07642_amd import Sim, inputs
+    from paper_1810_07642_amd import inputs
 
     n = args.n
+    sites = n * n
     p, h0, th = inputs.patterned_dewetting(n=n)
-    # FP32 storage as deviations from the rest equilibrium at the mean film height
-    href = 0.1
 
     if args.profile_steps or args.profile_adjoint:
-        prec = "fp32" if args.profile_adjoint else args.profile_storage
-        sim = Sim(n, n, prec, href=0.0 if prec == "fp64" else href, **p).init(h0, th)
-        if args.profile_adjoint:
-            k = args.profile_adjoint
-            cap = torch.empty(k * sim.capture_bytes(), dtype=torch.uint8, device="cuda")
-            adj = torch.empty(sim.adj_bytes(), dtype=torch.uint8, device="cuda")
-            sim.step_capture(k, cap)
-            sim.adj_seed(adj, torch.zeros(n, n, dtype=torch.float64))
-            sim.adj_steps(adj, cap, k)
-        else:
-            sim.step(args.profile_steps)
-        torch.cuda.synchronize()
-        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
-        dst = torch.empty_like(src)
-        src.fill_(1.0)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        what = f"reverse pass over {args.profile_adjoint} captured" if args.profile_adjoint else f"{args.profile_steps}"
-        log(f"profile run: {what} {prec} steps at {n}^2 and a 1 GiB copy")
+        profile_run(args, p, h0, th)
         return
 
-    ms32, h32, m32 = run_form("fp32", p, h0, th, args.steps, args.warmup, href=href)
-    ms_step = ms32 / args.steps
-    sites = n * n
-    mlups = sites * args.steps / (ms32 * 1e-3) / 1e6
-    achieved = BYTES_PER_SITE["fp32"] * sites / (ms_step * 1e-3) / 1e9
-    traffic = committed_traffic()
+    extras = {}
+    ceiling = copy_ceiling(p, h0, th)
+    ceil_gbs = ceiling["record_copy_GBps"]
+    # untimed: every form advanced ACCURACY_STEPS steps (the state the timing
+    # starts from) and its accuracy against the FP64 path there
+    sims, accuracy = steady_sims(p, h0, th, forms=("fp64",) if args.no_extras else
+                                 ("fp64", "fp32", "fp32_href0", "fp16s"))
+    if not args.no_extras:
+        extras["accuracy"] = accuracy
+        log(f"accuracy after {ACCURACY_STEPS} steps: {accuracy}")
+
+    # headline: FP64, exactly --steps timed steps after --warmup untimed ones,
+    # continuing the workload from step ACCURACY_STEPS
+    ms64 = timed_steps(sims["fp64"], args.steps, args.warmup)
+    sims["fp64"].check()
+    ms_step = ms64 / args.steps
+    mlups = sites * args.steps / (ms64 * 1e-3) / 1e6
+    launch_ms = ms64 / launches(args.steps)
+    roof = roofline_block("step_kernel<fp64, kappa field, 2 fused steps>", BYTES_PER_SITE["fp64"] * sites,
+                          launch_ms, committed_traffic("fp64"), ceil_gbs)
+    roof["per_step_equivalent_GBps"] = round(BYTES_PER_SITE["fp64"] * sites / (ms_step * 1e-3) / 1e9, 1)
     line = {
         "metric": "D2Q9 thin-film MLUPS, % HBM roofline, FP32/FP64 speedup, adjoint/forward time",
         "value": round(mlups, 1),
@@ -324,66 +450,61 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"patterned-substrate dewetting {n}x{n}, FP32 storage, stripe theta field",
-                   "nx": n, "ny": n, "storage": "fp32", "href": href, "theta": "stripes pi/9 | pi/4, period 256",
+        "config": {"workload": f"patterned-substrate dewetting {n}x{n}, FP64 storage and arithmetic, "
+                               "stripe theta field",
+                   "nx": n, "ny": n, "storage": "fp64", "theta": "stripes pi/9 | pi/4, period 256",
                    "hstar": p["hstar"], "tau": p["tau"], "gamma": p["gamma"], "delta": p["delta"]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if traffic is None else round(traffic[0] / (traffic[1] * ms_step * 1e-3) / 1e9, 1),
-                     "kernel": "step_kernel<fp32, kappa field, 2 fused steps>", "site_updates_per_launch": 2,
-                     "bytes_per_site_update": BYTES_PER_SITE["fp32"],
-                     # one launch advances two steps but reads and writes every record once:
-                     # frac above counts the bytes of two separate steps, per_pass the bytes of one pass
-                     "per_pass": {"bytes_per_site": BYTES_PER_SITE["fp32"],
-                                  "achieved": round(achieved / 2, 1),
-                                  "frac": round(achieved / 2 / HBM_PEAK_GBS, 4)}},
+        "roofline": roof,
     }
-    log(f"fp32: {ms_step * 1e3:.1f} us/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s algorithmic")
+    log(f"fp64: {ms_step * 1e3:.1f} us/step, {mlups:.0f} MLUPS, per pass {roof['achieved']:.0f} GB/s "
+        f"({roof['frac']:.3f} of peak), record copy {ceil_gbs:.0f} GB/s")
 
     if not args.no_extras:
-        extras = {}
-        k64 = max(50, args.steps // 4) // 2 * 2
-        ms64, h64, m64 = run_form("fp64", p, h0, th, k64, 20)
-        ms16, h16, m16 = run_form("fp16s", p, h0, th, args.steps, args.warmup, href=href)
-        mlups64 = sites * k64 / (ms64 * 1e-3) / 1e6
-        mlups16 = sites * args.steps / (ms16 * 1e-3) / 1e6
-        # accuracy against the FP64 path after the same number of steps
-        from paper_1810_07642_amd import Sim as _S
-        total = args.steps + args.warmup
-        s64 = _S(n, n, "fp64", **p).init(h0, th)
-        s64.step(total)
-        h64ref = s64.height()
-        del s64
+        extras["ceiling"] = ceiling
+        forms = {}
+        for prec in ("fp64", "fp32", "fp16s"):
+            ms = timed_steps(sims[prec], EXTRA_STEPS, 50)
+            sims[prec].check()
+            ml = sites * EXTRA_STEPS / (ms * 1e-3) / 1e6
+            lm = ms / launches(EXTRA_STEPS)
+            forms[prec] = {"mlups": round(ml, 1), "ms_per_step": round(ms / EXTRA_STEPS, 5),
+                           "steps_timed": EXTRA_STEPS, "href": HREF[prec],
+                           "roofline": roofline_block(f"step_kernel<{prec}, kappa field, 2 fused steps>",
+                                                      BYTES_PER_SITE[prec] * sites, lm, committed_traffic(prec),
+                                                      ceil_gbs)}
+            forms[prec]["roofline"]["per_step_equivalent_GBps"] = round(
+                BYTES_PER_SITE[prec] * sites / (ms / EXTRA_STEPS * 1e-3) / 1e9, 1)
+        for prec in ("fp32", "fp16s"):
+            forms[prec]["speedup_over_fp64"] = round(forms[prec]["mlups"] / forms["fp64"]["mlups"], 3)
+        extras["forms"] = forms
+        extras["timing_starts_after_steps"] = ACCURACY_STEPS
+        del sims
         torch.cuda.empty_cache()
-        scale = float(h64ref.abs().max())
-        extras["fp64"] = {"mlups": round(mlups64, 1), "ms_per_step": round(ms64 / k64, 5),
-                          "hbm_frac": round(BYTES_PER_SITE["fp64"] * mlups64 * 1e6 / 1e9 / HBM_PEAK_GBS, 4)}
-        extras["fp16s"] = {"mlups": round(mlups16, 1), "ms_per_step": round(ms16 / args.steps, 5),
-                           "hbm_frac": round(BYTES_PER_SITE["fp16s"] * mlups16 * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
-                           "max_rel_dh_vs_fp64": float((h16 - h64ref).abs().max()) / scale}
-        extras["fp32_max_rel_dh_vs_fp64"] = float((h32 - h64ref).abs().max()) / scale
-        _, h32p, _ = run_form("fp32", p, h0, th, args.steps, args.warmup, href=0.0)
-        extras["fp32_href0_max_rel_dh_vs_fp64"] = float((h32p - h64ref).abs().max()) / scale
-        del h32p
-        extras["accuracy_after_steps"] = total
-        ms1, _, _ = run_form("fp32", p, h0, th, k64, 20, fuse=1, href=href)
-        extras["fp32_one_step_per_pass"] = {"mlups": round(sites * k64 / (ms1 * 1e-3) / 1e6, 1),
-                                            "ms_per_step": round(ms1 / k64, 5)}
-        extras["fp64_mlups_by_lattice"] = fp64_by_lattice(mlups64)
-        extras["fp32_over_fp64_speedup"] = round(mlups / mlups64, 3)
-        extras["fp16s_over_fp64_speedup"] = round(mlups16 / mlups64, 3)
-        m0 = float(h0.sum())
-        extras["mass_rel_drift"] = {"fp32": (m32 - m0) / m0, "fp16s": (m16 - m0) / m0}
-        del h16, h64ref
+        log("forms: " + ", ".join(f"{k} {v['mlups']:.0f} MLUPS (pass frac {v['roofline']['frac']:.3f})"
+                                  for k, v in forms.items()))
+        s1 = make_sim("fp32", p, h0, th, fuse=1)
+        s1.step(ACCURACY_STEPS)
+        ms1 = timed_steps(s1, EXTRA_STEPS, 20)
+        del s1
+        extras["fp32_one_step_per_pass"] = {"mlups": round(sites * EXTRA_STEPS / (ms1 * 1e-3) / 1e6, 1),
+                                            "ms_per_step": round(ms1 / EXTRA_STEPS, 5)}
+        extras["fp64_mlups_by_lattice"] = fp64_by_lattice(forms["fp64"]["mlups"])
+        adj32, g32 = inverse_design_case("fp32")
+        _, g64 = inverse_design_case("fp64", reps=1)
+        rel = [float((a - b).norm() / b.norm()) for a, b in zip(g32, g64)]
+        adj32["fp32_forward_grad_rel_l2_vs_fp64"] = {"h0": rel[0], "theta": rel[1]}
+        extras["adjoint"] = adj32
+        del g32, g64
         torch.cuda.empty_cache()
-        extras["adjoint"] = adjoint_ratio()
-        # the same case with every step's capture kept (K = 0: no checkpoints, no recompute)
-        extras["adjoint_all_captures_kept"] = adjoint_ratio(K=0)
-        extras["reverse_sweep_at_headline_size"] = reverse_sweep_at(n)
+        extras["adjoint_all_captures_kept"] = inverse_design_case("fp32", K=0)[0]
+        extras["reverse_sweep_at_headline_size"] = reverse_sweep_at(n, ceil_gbs)
+        extras["paper_context"] = {
+            "note": "the paper's FP64 MLUPS table (Sec. IV), other hardware and code: context, not a target",
+            "gtx1080ti_fp64_mlups_4096": 395.6, "i7_4790_one_core_fp64_mlups_4096": 4.3}
         line["extras"] = extras
-        log(f"fp64 {mlups64:.0f} MLUPS, fp16s {mlups16:.0f} MLUPS, adjoint/forward {extras['adjoint']['ratio']:.2f}")
+        log(f"adjoint/forward {adj32['ratio']:.2f} (512^2, K = 64), fp32-forward gradient error {rel}")
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, h0, th)

@@ -463,19 +463,27 @@ int tflbm_check(const tflbm_sim *sim, tflbm_stream_t stream) {
 
 size_t tflbm_state_bytes(const tflbm_sim *sim) { return sim ? sim->pop_bytes : 0; }
 
+// A population buffer is whole 128-byte lines; the record-copy kernel moves it
+// when both ends are 16-byte aligned (the workspace always is), the runtime's
+// copy otherwise.
+static hipError_t copy_state(const void *src, void *dst, size_t bytes, hipStream_t st) {
+  if (((uintptr_t)src & 15) == 0 && ((uintptr_t)dst & 15) == 0 && bytes % 16 == 0)
+    return launch_copy(src, dst, bytes, st);
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+}
+
 int tflbm_state_save(const tflbm_sim *sim, void *d_dst, tflbm_stream_t stream) {
   if (!sim || !d_dst) return TFLBM_EINVAL;
   if (!sim->initialised) return TFLBM_ESTATE;
   const char *src = sim->ws + (sim->cur == 0 ? sim->off_a : sim->off_b);
-  return hip_status(sim, hipMemcpyAsync(d_dst, src, sim->pop_bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return hip_status(sim, copy_state(src, d_dst, sim->pop_bytes, (hipStream_t)stream));
 }
 
 int tflbm_state_load(tflbm_sim *sim, const void *d_src, int64_t step, tflbm_stream_t stream) {
   if (!sim || !d_src || step < 0) return TFLBM_EINVAL;
   if (!sim->initialised) return TFLBM_ESTATE;
   char *dst = sim->ws + (sim->cur == 0 ? sim->off_a : sim->off_b);
-  const int rc =
-      hip_status(sim, hipMemcpyAsync(dst, d_src, sim->pop_bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  const int rc = hip_status(sim, copy_state(d_src, dst, sim->pop_bytes, (hipStream_t)stream));
   if (rc) return rc;
   sim->steps = step;
   return TFLBM_OK;

@@ -938,6 +938,47 @@ __global__ __launch_bounds__(256) void mass_final_kernel(const double *partial, 
   if (threadIdx.x == 0) out[0] = base + ((red[0] + red[1]) + (red[2] + red[3]));
 }
 
+// ---- record copy: checkpoints, and the bandwidth ceiling of one pass ------------
+// Copies n16 16-byte words (a population buffer is whole 128-byte lines).
+// Workgroup b streams the contiguous range [b per_block, (b + 1) per_block);
+// each lane has four 16-byte loads in flight before its stores.  Loads and
+// stores are non-temporal: nothing reads the copied bytes again soon.  A pass
+// of the step reads and writes every record once plus its halo re-reads, so
+// this copy's rate is the most that pass could reach on this GPU.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void copy_kernel(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
+                                                   int64_t n16, int64_t per_block) {
+  const int64_t begin = (int64_t)blockIdx.x * per_block;
+  const int64_t end = begin + per_block < n16 ? begin + per_block : n16;
+  for (int64_t i = begin + threadIdx.x; i < end; i += 4 * 256) {
+    u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * 256 < end) v[u] = __builtin_nontemporal_load(src + i + u * 256);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * 256 < end) __builtin_nontemporal_store(v[u], dst + i + u * 256);
+  }
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return hipSuccess;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  constexpr int64_t kStride = 4 * 256;  // words per workgroup iteration
+  int64_t nb = (n16 + kStride - 1) / kStride;
+  if (nb > 16LL * cus) nb = 16LL * cus;  // eight 256-thread workgroups per CU, two rounds
+  int64_t per = (n16 + nb - 1) / nb;
+  per = (per + kStride - 1) / kStride * kStride;
+  nb = (n16 + per - 1) / per;
+  copy_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>((const u32x4 *)src, (u32x4 *)dst, n16, per);
+  return hipGetLastError();
+}
+
 // ---- launchers -----------------------------------------------------------------
 template <int P, int NS, bool G0>
 static void launch_step_v(const StepArgs &A, bool kf, bool cap, hipStream_t s) {

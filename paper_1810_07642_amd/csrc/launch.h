@@ -25,6 +25,9 @@ hipError_t launch_init(int prec, const StepArgs &A, const double *h0, const doub
                        hipStream_t s);
 hipError_t launch_read(int prec, const StepArgs &A, double *h, double *ux, double *uy, hipStream_t s);
 hipError_t launch_mass(int prec, const StepArgs &A, double *partial, int np, double *out, hipStream_t s);
+// Device-to-device copy of `bytes` (a multiple of 16; both pointers 16-byte
+// aligned) by the library's record-copy kernel.
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // Reverse-mode kernels.
 struct AdjArgs;

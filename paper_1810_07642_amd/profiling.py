@@ -1,0 +1,299 @@
+"""rocprofv3 summaries of the library's kernels, and reading them back.
+
+The roofline figures of ``bench.py`` compare a kernel's algorithmic bytes per
+launch with its launch time; the HBM bytes it really moves come from two
+rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+scaled by what the same counter reads for a 1 GiB device-to-device copy of
+known size.  This module turns the CSV output of those runs (and of a
+``--kernel-trace --stats`` run, and optionally of an SQ instruction-counter
+run) into a short markdown summary under ``profiles/``, with machine-readable
+lines that ``bench.py`` reads:
+
+    kernel_source_sha256: <hash of the kernel and launch-plan sources>
+    traffic_bytes_per_launch: <calibrated HBM bytes per dispatch>
+    steps_per_launch: <time steps one dispatch advances>
+    avg_launch_ns: <mean dispatch duration in the counter runs>
+
+A summary is used only while its hash matches the current sources (comments
+and blank lines do not count), so a kernel edit invalidates it.
+
+    python -m paper_1810_07642_amd.profiling step --storage fp64 \\
+        --fetch DIR --write DIR [--sq DIR] --out profiles/step_fp64_dewetting4096_traffic.md
+    python -m paper_1810_07642_amd.profiling adjoint --fetch DIR --write DIR [--sq DIR] --out ...
+    python -m paper_1810_07642_amd.profiling trace --trace DIR --out ... --command "..."
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import re
+import statistics
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+
+# Sources a kernel's traffic depends on: the kernel and the launch plan that
+# sets its tiles (hence its halo re-reads).
+STEP_SOURCES = [os.path.join(CSRC, f) for f in ("fwd.hip", "device.h", "api.hip")]
+ADJ_SOURCES = [os.path.join(CSRC, f) for f in ("adj.hip", "device.h", "api.hip")]
+
+N4096 = 4096 * 4096
+# Algorithmic bytes per site of one pass of the fused two-step kernel: every
+# record read and written once (9 populations) plus the kappa field read once.
+STEP_BYTES = {"fp64": (80, 72), "fp32": (40, 36), "fp16s": (24, 20)}  # (read, write) per site
+STEP_KERNEL_PREC = {"fp64": 0, "fp32": 1, "fp16s": 2}
+# The two-step reverse pass (FP32 adjoint): adjoint 36 + two captures 24 +
+# kappa 4 + g_kappa 8 read; adjoint 36 + g_kappa 8 written.
+ADJ_BYTES = (72, 44)
+CALIB_BYTES = 1 << 30  # the 1 GiB calibration copy
+CLOCK_GHZ = 2.4
+SIMDS = 256 * 4
+
+
+def source_hash(paths):
+    """Hash of the given sources with comments and blank lines removed."""
+    h = hashlib.sha256()
+    for p in paths:
+        text = open(p).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
+    return h.hexdigest()[:16]
+
+
+def read_summary(path, sources):
+    """(traffic bytes per launch, steps per launch, avg launch ns) from a
+    committed summary taken on the current sources, else None."""
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    m_steps = re.search(r"steps_per_launch:\s*([0-9]+)", text)
+    m_ns = re.search(r"avg_launch_ns:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != source_hash(sources):
+        return None
+    return (float(m_val.group(1)), int(m_steps.group(1)) if m_steps else 1,
+            float(m_ns.group(1)) if m_ns else None)
+
+
+# ---- rocprofv3 CSV ---------------------------------------------------------------
+
+def _find(dirpath, suffix):
+    hits = sorted(glob.glob(os.path.join(dirpath, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {dirpath}")
+    return hits
+
+
+def _rows(path):
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def counters(dirpath):
+    """{(kernel name, grid size): {counter: [value per dispatch]}} from a
+    --pmc run (values of one dispatch summed over the counter's instances)."""
+    out = {}
+    for path in _find(dirpath, "counter_collection.csv"):
+        per = {}
+        for r in _rows(path):
+            key = (r["Kernel_Name"], int(r.get("Grid_Size", 0) or 0), r["Dispatch_Id"])
+            per.setdefault(key, {}).setdefault(r["Counter_Name"], 0.0)
+            per[key][r["Counter_Name"]] += float(r["Counter_Value"])
+        for (name, grid, _), vals in per.items():
+            d = out.setdefault((name, grid), {})
+            for c, v in vals.items():
+                d.setdefault(c, []).append(v)
+    return out
+
+
+def trace(dirpath):
+    """{(kernel name, grid size): [duration ns per dispatch]} from a
+    --kernel-trace run."""
+    out = {}
+    for path in _find(dirpath, "kernel_trace.csv"):
+        for r in _rows(path):
+            grid = int(r.get("Grid_Size_X", r.get("Grid_Size", 0)) or 0)
+            dur = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+            out.setdefault((r["Kernel_Name"], grid), []).append(dur)
+    return out
+
+
+def _pick(table, pattern, grid=None):
+    """The (name, grid) entry whose name matches `pattern` (and whose grid is
+    `grid`, if given): the one with the most dispatches."""
+    cands = [(k, v) for k, v in table.items() if re.search(pattern, k[0]) and (grid is None or k[1] == grid)]
+    if not cands:
+        raise KeyError(f"no kernel matching {pattern!r}" + ("" if grid is None else f" with grid {grid}"))
+
+    def count(item):
+        v = item[1]
+        return len(next(iter(v.values()))) if isinstance(v, dict) else len(v)
+    return max(cands, key=count)
+
+
+def _calibration(fetch, write):
+    """Bytes moved per counter byte of the 1 GiB runtime copy: (fetch, write)."""
+    _, fv = _pick(fetch, r"[Cc]opy[Bb]uffer")
+    _, wv = _pick(write, r"[Cc]opy[Bb]uffer")
+    f_kib = statistics.mean(fv["FETCH_SIZE"])
+    w_kib = statistics.mean(wv["WRITE_SIZE"])
+    return CALIB_BYTES / (f_kib * 1024.0), CALIB_BYTES / (w_kib * 1024.0), f_kib, w_kib
+
+
+def _sq_lines(sq, pattern, grid, dur_ns):
+    _, vals = _pick(sq, pattern, grid)
+    mean = {c: statistics.mean(v) for c, v in vals.items()}
+    lines = ["", "SQ instruction counters of the same kernel (means over its dispatches in the counter run):", "",
+             "| counter | per launch |", "|---|---|"]
+    for c in sorted(mean):
+        lines.append(f"| {c} | {mean[c]:.4g} |")
+    if dur_ns:
+        cyc = dur_ns * CLOCK_GHZ
+        lines.append("")
+        if "SQ_INSTS_VALU" in mean:
+            # a wave64 VALU instruction holds a 16-lane SIMD for 4 cycles, FP64
+            # FMA included (78.6 TFLOP/s = 1024 SIMDs x 16 lanes x 2 x 2.4 GHz);
+            # transcendental and packed forms take longer, so this is a lower
+            # bound of the busy share
+            issue = mean["SQ_INSTS_VALU"] * 4.0 / (SIMDS * cyc)
+            lines.append(f"VALU issue share: SQ_INSTS_VALU x 4 cycles / ({SIMDS} SIMDs x {cyc:.4g} cycles of a "
+                         f"{dur_ns / 1e3:.1f} us launch at {CLOCK_GHZ} GHz) = {issue:.3f}")
+            lines.append(f"valu_issue_share: {issue:.4f}")
+        if "SQ_ACTIVE_INST_VALU" in mean:
+            act = mean["SQ_ACTIVE_INST_VALU"] * 4.0 / (SIMDS * cyc)
+            lines.append(f"VALU active share: SQ_ACTIVE_INST_VALU x 4 / ({SIMDS} SIMDs x launch cycles) = {act:.3f}")
+        if "SQ_INSTS_LDS" in mean and "SQ_WAVES" in mean:
+            lines.append(f"LDS instructions per wavefront: {mean['SQ_INSTS_LDS'] / mean['SQ_WAVES']:.0f}")
+    return lines
+
+
+def traffic_summary(title, kernel_desc, pattern, fetch_dir, write_dir, alg_read, alg_write, steps_per_launch,
+                    sources, commands, notes=(), sq_dir=None, trace_dir=None, alg_desc=""):
+    fetch, write = counters(fetch_dir), counters(write_dir)
+    cf, cw, cf_kib, cw_kib = _calibration(fetch, write)
+    (kname, grid), fv = _pick(fetch, pattern)
+    _, wv = _pick(write, pattern, grid)
+    f_kib = statistics.mean(fv["FETCH_SIZE"])
+    w_kib = statistics.mean(wv["WRITE_SIZE"])
+    rd = f_kib * 1024.0 * cf
+    wr = w_kib * 1024.0 * cw
+    dur = None
+    if trace_dir:
+        t = trace(trace_dir)
+        # trace grids count workgroups x 64 lanes like the counter runs' Grid_Size
+        hits = [d for (name, g), d in t.items() if name == kname and g == grid]
+        if hits:
+            dur = statistics.mean(hits[0])
+    lines = [f"# {title}", "", f"Kernel: `{kname}` ({kernel_desc}), grid {grid} lanes.", "",
+             "Commands (each a run of its own, on one MI355X; <repo> is the repository root):", "",
+             "    cd /tmp && export TMPDIR=/tmp"]
+    lines += [f"    {c}" for c in commands]
+    lines += ["", "| kernel | dispatches | FETCH_SIZE (KiB/dispatch) | WRITE_SIZE (KiB/dispatch) |", "|---|---|---|---|",
+              f"| {kname.split('(')[0]} | {len(fv['FETCH_SIZE'])} | {f_kib:.1f} | {w_kib:.1f} |",
+              f"| 1 GiB runtime copy | 1 | {cf_kib:.1f} | {cw_kib:.1f} |", "",
+              f"Calibration (bytes moved / counter bytes of the 1 GiB copy): fetch x {cf:.4f}, write x {cw:.4f}.", "",
+              f"| per launch ({steps_per_launch} step{'s' if steps_per_launch > 1 else ''}) | read | write | total |",
+              "|---|---|---|---|",
+              f"| measured HBM bytes (calibrated) | {rd / 1e6:.1f} MB | {wr / 1e6:.1f} MB | {(rd + wr) / 1e6:.1f} MB |",
+              f"| algorithmic{': ' + alg_desc if alg_desc else ''} | {alg_read / 1e6:.1f} MB | {alg_write / 1e6:.1f} MB | "
+              f"{(alg_read + alg_write) / 1e6:.1f} MB |",
+              f"| measured / algorithmic | {rd / alg_read:.3f} | {wr / alg_write:.3f} | "
+              f"{(rd + wr) / (alg_read + alg_write):.3f} |"]
+    if dur:
+        lines += ["", f"Mean launch duration in the traced bench run: {dur / 1e3:.1f} us: "
+                      f"{(alg_read + alg_write) / dur:.1f} GB/s algorithmic "
+                      f"({(alg_read + alg_write) / dur / 8000.0:.3f} of 8 TB/s), "
+                      f"{(rd + wr) / dur:.1f} GB/s measured HBM traffic."]
+    lines += [""] + list(notes)
+    if sq_dir:
+        lines += _sq_lines(counters(sq_dir), re.escape(kname), grid, dur)
+    lines += ["", f"kernel_source_sha256: {source_hash(sources)}",
+              f"traffic_bytes_per_launch: {rd + wr:.6e}",
+              f"algorithmic_bytes_per_launch: {alg_read + alg_write:.6e}",
+              f"steps_per_launch: {steps_per_launch}"]
+    if dur:
+        lines.append(f"avg_launch_ns: {dur:.1f}")
+    return "\n".join(lines) + "\n"
+
+
+def trace_summary(trace_dir, command, title):
+    t = trace(trace_dir)
+    lines = [f"# {title}", "", "Command (one MI355X; <repo> is the repository root):", "",
+             "    cd /tmp && export TMPDIR=/tmp", f"    {command}", "",
+             "Per kernel and grid (lanes = workgroups x 64), durations in ns from the kernel trace:", "",
+             "| kernel | grid | launches | avg | median | min | max |", "|---|---|---|---|---|---|---|"]
+    for (name, grid), d in sorted(t.items(), key=lambda kv: -sum(kv[1])):
+        short = name.split("(")[0]
+        lines.append(f"| `{short}` | {grid} | {len(d)} | {statistics.mean(d):.0f} | {statistics.median(d):.0f} | "
+                     f"{min(d):.0f} | {max(d):.0f} |")
+    return "\n".join(lines) + "\n"
+
+
+def _step_cmds(storage):
+    base = f"python3 <repo>/bench.py --profile-steps 20 --profile-storage {storage}"
+    return [f"rocprofv3 --pmc {c} --output-format csv -d <repo>/gpurun_out/step_{storage}_{c} -o run -- {base}"
+            for c in ("FETCH_SIZE", "WRITE_SIZE")]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("step")
+    s.add_argument("--storage", choices=("fp64", "fp32", "fp16s"), required=True)
+    a = sub.add_parser("adjoint")
+    for p in (s, a):
+        p.add_argument("--fetch", required=True)
+        p.add_argument("--write", required=True)
+        p.add_argument("--sq")
+        p.add_argument("--sq-command", default="")
+        p.add_argument("--trace", help="kernel-trace run of the bench (launch durations)")
+        p.add_argument("--out", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("--trace", required=True)
+    t.add_argument("--command", required=True)
+    t.add_argument("--title", default="Kernel trace")
+    t.add_argument("--out", required=True)
+    args = ap.parse_args(argv)
+    if args.what == "trace":
+        text = trace_summary(args.trace, args.command, args.title)
+    elif args.what == "step":
+        r, w = STEP_BYTES[args.storage]
+        cmds = _step_cmds(args.storage)
+        if args.sq_command:
+            cmds.append(args.sq_command)
+        text = traffic_summary(
+            f"HBM traffic of the {args.storage.upper()} step kernel, patterned dewetting 4096 x 4096",
+            f"{args.storage.upper()} storage, kappa field, 2 time steps per launch",
+            rf"step_kernel<{STEP_KERNEL_PREC[args.storage]}, true, false, 2,", args.fetch, args.write,
+            r * N4096, w * N4096, 2, STEP_SOURCES, cmds, sq_dir=args.sq, trace_dir=args.trace,
+            alg_desc=f"records read and written once and the kappa field read once ({r}/{w} B/site)",
+            notes=["`bench.py --profile-steps 20` runs 20 steps (10 launches) of the benchmark workload, "
+                   "a record copy of one population buffer (tflbm_state_save) and a 1 GiB runtime copy "
+                   "that calibrates the counters."])
+    else:
+        cmds = [f"rocprofv3 --pmc {c} --output-format csv -d <repo>/gpurun_out/adj_{c} -o run -- "
+                f"python3 <repo>/bench.py --profile-adjoint 16" for c in ("FETCH_SIZE", "WRITE_SIZE")]
+        if args.sq_command:
+            cmds.append(args.sq_command)
+        text = traffic_summary(
+            "Reverse pass, two steps per launch: FP32 adjoint, patterned dewetting 4096 x 4096",
+            "FP32 adjoint, kappa field, two reverse time steps per launch", r"adj_step2_kernel<float, true>",
+            args.fetch, args.write, ADJ_BYTES[0] * N4096, ADJ_BYTES[1] * N4096, 2, ADJ_SOURCES, cmds, sq_dir=args.sq,
+            trace_dir=args.trace,
+            alg_desc="adjoint 36 + two captures 24 + kappa 4 + g_kappa 8 read; adjoint 36 + g_kappa 8 written (B/site)",
+            notes=["`bench.py --profile-adjoint 16` captures 16 FP32 steps of the benchmark workload, runs the "
+                   "reverse pass over them (8 launches of the two-step kernel), then a 1 GiB runtime copy that "
+                   "calibrates the counters."])
+    with open(args.out, "w") as fh:
+        fh.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    main()
