@@ -17,11 +17,14 @@ def random_case(ny, nx, seed, hlo=0.3, hhi=0.6, tlo=0.2, thi=0.7):
     return h0, th
 
 
-def oracle_run(params, h0, th, steps):
+def oracle_run(params, h0, th, steps, with_moving=False):
+    """(h, ux, uy, mass) of the oracle after `steps` steps; with_moving also
+    returns max |f_l|, l >= 1, of the final state (the FP16S bound)."""
     P = lbm.Params(**params)
     f = lbm.run(lbm.init(h0, P), lbm.kappa(th, P), P, steps)
     h, ux, uy = lbm.readout(f)
-    return h, ux, uy, lbm.mass(f)
+    out = (h, ux, uy, lbm.mass(f))
+    return out + (float(f[1:].abs().max()),) if with_moving else out
 
 
 def gpu_run(params, h0, th, steps, prec, theta_field=True, **extra):
@@ -54,6 +57,82 @@ def fp32_tol(steps):
     the dissipative step does not amplify them, so the error stays below
     30 u per step, accumulated linearly."""
     return 30.0 * U32 * max(1, steps)
+
+
+def fp16s_tol(steps, fmov_over_h):
+    """A-priori bound for FP16S storage relative to max h: the FP32 bound plus,
+    per step, 8 moving populations rounded to FP16 (relative error 2^-12 of a
+    value at most max |f_moving|) feeding each new h."""
+    return fp32_tol(steps) + max(1, steps) * 8 * 2.0 ** -12 * fmov_over_h
+
+
+# Errors of the FP32 and FP16S comparisons observed on the MI355X, per case
+# (max |dh| / the case's scale; gradients: relative L2).  A comparison passes
+# if its error is within its a-priori bound (fp32_tol, fp16s_tol) and within
+# OBS_FACTOR times the error observed for the case.  The FP32 forms are
+# deterministic, so the factor only leaves room for a change of rounding
+# (compiler, operation order); a slip of the size the a-priori bounds allow
+# (100-1000 times the observed errors) fails.
+OBS_FACTOR = 10.0
+# observed on the MI355X (one run of the GPU test suite, printed on its OBS lines)
+OBSERVED = {
+    "design512x4096.fp32.href0.dh0_vs_fp64": 1.157e-04,
+    "design512x4096.fp32.href0.dtheta_vs_fp64": 4.871e-04,
+    "design64x256.fp16s.href0.1.dh0": 1.610e-06,
+    "design64x256.fp16s.href0.1.dtheta": 1.642e-06,
+    "design64x256.fp32.href0.0.dh0": 4.700e-05,
+    "design64x256.fp32.href0.0.dtheta": 5.603e-05,
+    "design64x256.fp32.href0.1.dh0": 1.602e-06,
+    "design64x256.fp32.href0.1.dtheta": 1.645e-06,
+    "design64x4096.fp16s.dh0": 1.908e-04,
+    "design64x4096.fp16s.dtheta": 2.891e-06,
+    "design64x4096.fp32.dh0": 1.911e-04,
+    "design64x4096.fp32.dtheta": 2.891e-06,
+    "dewetting256x2000.fp16s.href0.1": 2.764e-05,
+    "dewetting256x2000.fp32.href0.0": 5.684e-05,
+    "dewetting256x2000.fp32.href0.1": 1.974e-05,
+    "dewetting4096x4.fp16s.href0.1": 1.090e-05,
+    "dewetting4096x4.fp32.href0.1": 2.562e-08,
+    "exponents10_4.fp32": 3.872e-06,
+    "exponents2_3.fp32": 1.413e-06,
+    "exponents3_6.fp32": 2.051e-06,
+    "exponents3_9.fp32": 2.422e-06,
+    "exponents4_10.fp32": 4.463e-06,
+    "hanging512x500.amp.fp16s.fp16_scale_log218.href1.0": 9.847e-06,
+    "hanging512x500.amp.fp32.href1.0": 1.913e-06,
+    "href0.45.case0.fp32": 7.734e-07,
+    "href0.45.case2.fp32": 6.360e-07,
+    "href0.45.case3.fp32": 4.781e-07,
+    "href0.8.case0.fp32": 5.914e-06,
+    "href0.8.case2.fp32": 2.173e-06,
+    "href0.8.case3.fp32": 1.350e-06,
+    "parity.case0.fp16s": 7.200e-06,
+    "parity.case0.fp32": 7.009e-06,
+    "parity.case1.fp16s": 2.291e-05,
+    "parity.case1.fp32": 2.740e-06,
+    "parity.case2.fp16s": 8.688e-06,
+    "parity.case2.fp32": 3.419e-06,
+    "parity.case5.fp16s": 5.223e-06,
+    "parity.case5.fp32": 4.631e-06,
+    "sampled32768x2.fp32.href0.1": 9.417e-09,
+    "sampled4096x5.fp16s.href0.1": 2.765e-06,
+    "sampled4096x5.fp32.href0.0": 3.427e-07,
+    "sampled4096x5.fp32.href0.1": 1.517e-08,
+    "sliding1024x512x300.fp16s.href0.5": 1.135e-05,
+    "sliding1024x512x300.fp32.href0.5": 1.125e-06,
+    "smallamp64x2000.fp32.href1": 3.399e-06,
+    "spreading512x200.fp16s.href0.5": 1.390e-06,
+    "spreading512x200.fp32.href0.5": 1.234e-05,
+}
+
+
+def check_err(case, err, apriori):
+    """Prints the observed error of `case` on an OBS line and asserts it
+    against the a-priori bound and OBS_FACTOR x the recorded observation."""
+    print(f"OBS {case} {err:.3e} (a-priori bound {apriori:.3e})", flush=True)
+    assert err <= apriori, (case, err, apriori)
+    if case in OBSERVED:
+        assert err <= OBS_FACTOR * OBSERVED[case], (case, err, OBSERVED[case])
 
 
 def banner(msg):
