@@ -88,6 +88,8 @@ typedef struct tflbm_params {
   int32_t prec;            /* TFLBM_FP64, TFLBM_FP32 or TFLBM_FP16S */
   int32_t n_exp, m_exp;    /* disjoining exponents n != m, 1..32 (paper: 9 and 3) */
   int32_t fp16_scale_log2; /* TFLBM_FP16S scale exponent s, 0..24 */
+  int32_t gamma_field;     /* 0, or 1: the surface tension is a per-site field given to tflbm_init_fields
+                              (the workspace then holds two values per site instead of kappa) */
   double tau;              /* BGK relaxation time, > 1/2 */
   double gamma;            /* surface tension, >= 0 */
   double g;                /* gravity in the equilibrium's g h^2/2; < 0 destabilises */
@@ -139,8 +141,9 @@ int tflbm_create(const tflbm_params *p, tflbm_sim **out);
 void tflbm_destroy(tflbm_sim *sim);
 
 /* Bytes of device workspace the handle needs: two population buffers, the
- * kappa field, a status word and reduction partials.  Depends only on the
- * parameters. */
+ * kappa field (or, with params.gamma_field, the per-site pair
+ * (-gamma/6, -gamma kappa)), a status word and reduction partials.  Depends
+ * only on the parameters. */
 size_t tflbm_workspace_bytes(const tflbm_sim *sim);
 
 /* Attaches a caller-allocated device workspace of `bytes` >= tflbm_workspace_bytes
@@ -157,6 +160,21 @@ int tflbm_bind(tflbm_sim *sim, void *d_ws, size_t bytes);
  * to 0 and clears the status word; releases the step graphs of an earlier
  * init (after waiting for the device). */
 int tflbm_init(tflbm_sim *sim, const double *d_h0, const double *d_theta, tflbm_stream_t stream);
+
+/* (async) tflbm_init with a position-dependent surface tension gamma(x)
+ * (Sec. II: the sentence after eq. "n_laplace" names such a field among those
+ * the stencils act on).  It replaces gamma in the film pressure,
+ *   p_film = -gamma(x) (lap h + kappa(x) f(h)),  F_film = -h grad p_film,
+ * so the isotropic gradient acts on the product (no Marangoni stress is
+ * added: the paper writes none).  d_gamma: [ny][nx] FP64, every value >= 0
+ * and finite (checked on the device; reported by tflbm_check), or NULL for
+ * params.gamma everywhere (then the steps are bit for bit those of a handle
+ * without the field).  Needs params.gamma_field = 1 (TFLBM_EINVAL otherwise);
+ * a handle with params.gamma_field = 1 reads the field in every step, also
+ * after tflbm_init.  The reverse pass (tflbm_adj_seed) refuses such a handle
+ * with TFLBM_EINVAL.  d_h0, d_theta as for tflbm_init. */
+int tflbm_init_fields(tflbm_sim *sim, const double *d_h0, const double *d_theta, const double *d_gamma,
+                      tflbm_stream_t stream);
 
 /* (async) Advances nsteps >= 0 time steps of eq. "LBE".  On lattices whose
  * steps are bound by launch latency (at most 2^20 sites; TFLBM_GRAPH), whole
@@ -177,8 +195,10 @@ int tflbm_step_graphs(const tflbm_sim *sim);
 int64_t tflbm_step_count(const tflbm_sim *sim);
 
 /* (async) Height h = sum_l f_l and velocity u = (sum_l c_l f_l)/h of the
- * current populations, computed in FP64 from the stored values.  Each output
- * is [ny][nx] FP64 device memory; any of them may be NULL to skip it. */
+ * current populations (the moments of Sec. II that define h and h u from the
+ * populations), computed in FP64 from the stored values.  Each output is
+ * [ny][nx] FP64 device memory; any of them may be NULL to skip it.
+ * TFLBM_ESTATE before tflbm_init. */
 int tflbm_read(const tflbm_sim *sim, double *d_h, double *d_ux, double *d_uy, tflbm_stream_t stream);
 
 /* (blocking) Total mass sum_{x,l} f_l(x) in FP64 (deterministic two-pass
@@ -201,7 +221,10 @@ int tflbm_mass(const tflbm_sim *sim, double *h_mass, tflbm_stream_t stream);
 int tflbm_mass_noalloc(const tflbm_sim *sim, double *d_mass, tflbm_stream_t stream);
 
 /* (blocking) TFLBM_OK, or TFLBM_ENONFINITE if a step since tflbm_init met
- * h <= 0 or a non-finite h at an updated site, or if h0 had such a value. */
+ * h <= 0 or a non-finite h at an updated site (the height moment of Sec. II,
+ * h = sum_l f_l, which divides the momentum in u = j/h and must stay positive
+ * for the film pressure's (h_*/h)^n), or if h0 (or a surface tension field)
+ * had an invalid value.  TFLBM_ESTATE before tflbm_init. */
 int tflbm_check(const tflbm_sim *sim, tflbm_stream_t stream);
 
 /* (blocking) Term-balance diagnostic (appendix, eq. "magnitude"): h_norms[0..7]
@@ -253,7 +276,8 @@ size_t tflbm_adj_bytes(const tflbm_sim *sim);
 
 /* (async) Starts a reverse pass in d_adj (tflbm_adj_bytes bytes, 256-byte
  * aligned): the adjoint of the final populations is dL/dh_N(x) for every l,
- * and the kappa gradient is zeroed.  d_grad_h: [ny][nx] FP64. */
+ * and the kappa gradient is zeroed.  d_grad_h: [ny][nx] FP64.  TFLBM_EINVAL
+ * for a handle with params.gamma_field = 1. */
 int tflbm_adj_seed(tflbm_sim *sim, void *d_adj, const double *d_grad_h, tflbm_stream_t stream);
 
 /* (async) Moves the adjoint from the end of step t to its start, using the

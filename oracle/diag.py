@@ -32,12 +32,13 @@ NAMES = ("pressure_x", "friction_x", "viscous_x", "advection_x",
          "pressure_y", "friction_y", "viscous_y", "advection_y")
 
 
-def term_fields(f, kap, p):
-    """The eight term fields of the module docstring, as a dict of [ny, nx] arrays."""
+def term_fields(f, kap, p, gam=None):
+    """The eight term fields of the module docstring, as a dict of [ny, nx]
+    arrays; ``gam``: optional per-site surface tension field."""
     h, jx, jy = lbm.moments(f)
     ux = jx / h
     uy = jy / h
-    pf = lbm.film_pressure(h, kap, p)
+    pf = lbm.film_pressure(h, kap, p, gam)
     gpx, gpy = lbm.gradient(pf)
     alpha = lbm.friction_coefficient(h, p.delta)
     djx_x, _ = lbm.gradient(jx)
@@ -66,6 +67,6 @@ def norm(phi):
     return math.sqrt(math.fsum((vals * vals).tolist()) / vals.numel())
 
 
-def term_norms(f, kap, p):
+def term_norms(f, kap, p, gam=None):
     """Norms of the eight term fields, a dict name -> float."""
-    return {k: norm(v) for k, v in term_fields(f, kap, p).items()}
+    return {k: norm(v) for k, v in term_fields(f, kap, p, gam).items()}

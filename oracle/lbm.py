@@ -34,6 +34,13 @@ the design notes):
   equilibrium is reproduced exactly, and the rounding of (1 - omega) + omega
   does not bias the total mass once per step.
 * Body force (Sec. II, after eq. "alphafric"): F = h (a_x, a_y).
+* Position-dependent surface tension (Sec. II, the sentence after eq.
+  "n_laplace", which names such a field among those the stencils apply to,
+  without writing its model): gamma(x) takes the place of gamma in eq.
+  "pfilm", p = -gamma(x) (lap h + kappa f(h)), and F_film = -h grad p as
+  before, so the gradient stencil acts on the product.  A Marangoni stress
+  at the free surface is not part of the paper's equations and is not
+  added.
 """
 import math
 
@@ -166,10 +173,13 @@ def disjoining_shape(h, p):
     return r ** p.n - r ** p.m
 
 
-def film_pressure(h, kap, p):
+def film_pressure(h, kap, p, gam=None):
     """p_film = -gamma (lap h + kappa f(h)) (Sec. II, eqs. "pfilm", "disjoiningP"),
-    with the disjoining sign read as described in the module docstring."""
-    return -p.gamma * (laplacian(h) + kap * disjoining_shape(h, p))
+    with the disjoining sign read as described in the module docstring;
+    ``gam``, if given, is a per-site surface tension field used instead of
+    p.gamma."""
+    g = p.gamma if gam is None else gam
+    return -g * (laplacian(h) + kap * disjoining_shape(h, p))
 
 
 def friction_coefficient(h, delta):
@@ -177,13 +187,13 @@ def friction_coefficient(h, delta):
     return 6.0 * h / (2.0 * h * h + 6.0 * delta * h + 3.0 * delta * delta)
 
 
-def total_force(h, ux, uy, kap, p):
+def total_force(h, ux, uy, kap, p, gam=None):
     """F_tot = F_film + F_fric + F (Sec. II, eq. "force").
 
     F_film = -h grad p_film (rho_0 = 1), F_fric = -nu alpha_delta(h) u
-    (eq. "forcefric"), F = h (ax, ay).
+    (eq. "forcefric"), F = h (ax, ay); ``gam``: optional surface tension field.
     """
-    pf = film_pressure(h, kap, p)
+    pf = film_pressure(h, kap, p, gam)
     gpx, gpy = gradient(pf)
     alpha = friction_coefficient(h, p.delta)
     fx = -h * gpx - p.nu * alpha * ux + h * p.ax
@@ -197,16 +207,17 @@ def init(h0, p):
     return torch.stack(equilibrium(h0, z, z, p.g))
 
 
-def step(f, kap, p):
+def step(f, kap, p, gam=None):
     """One time step of eq. "LBE" (Sec. II): BGK collision with forcing, then
     streaming f_l(x + c_l, t + 1) = post-collision f_l(x, t).
 
-    ``f`` holds the pre-collision populations at time t, shape [9, ny, nx].
+    ``f`` holds the pre-collision populations at time t, shape [9, ny, nx];
+    ``gam``: optional per-site surface tension field (else p.gamma).
     """
     h, jx, jy = moments(f)
     ux = jx / h
     uy = jy / h
-    fx, fy = total_force(h, ux, uy, kap, p)
+    fx, fy = total_force(h, ux, uy, kap, p, gam)
     feq = equilibrium(h, ux, uy, p.g)
     w = p.omega
     out = []
@@ -218,10 +229,10 @@ def step(f, kap, p):
     return torch.stack(out)
 
 
-def run(f, kap, p, nsteps):
+def run(f, kap, p, nsteps, gam=None):
     """Apply ``step`` nsteps times."""
     for _ in range(int(nsteps)):
-        f = step(f, kap, p)
+        f = step(f, kap, p, gam)
     return f
 
 

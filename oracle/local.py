@@ -30,13 +30,15 @@ def _windows(field, sites, R):
     return torch.stack(out)
 
 
-def sampled_run(h0, theta, p, nsteps, sites):
+def sampled_run(h0, theta, p, nsteps, sites, gamma=None):
     """Run ``nsteps`` oracle steps from f = E(h0) and return the height and
-    velocity at each (y, x) in ``sites`` as three float64 tensors [S]."""
+    velocity at each (y, x) in ``sites`` as three float64 tensors [S];
+    ``gamma``: optional surface tension field."""
     R = 3 * int(nsteps) + 2
     hw = _windows(h0.to(lbm.DTYPE), sites, R)
     tw = _windows(theta.to(lbm.DTYPE), sites, R)
+    gw = None if gamma is None else _windows(gamma.to(lbm.DTYPE), sites, R)
     kap = lbm.kappa(tw, p)
-    f = lbm.run(lbm.init(hw, p), kap, p, nsteps)
+    f = lbm.run(lbm.init(hw, p), kap, p, nsteps, gw)
     h, ux, uy = lbm.readout(f)
     return h[:, R, R].clone(), ux[:, R, R].clone(), uy[:, R, R].clone()

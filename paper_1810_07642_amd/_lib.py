@@ -26,6 +26,7 @@ class Params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("prec", ctypes.c_int32),
         ("n_exp", ctypes.c_int32), ("m_exp", ctypes.c_int32), ("fp16_scale_log2", ctypes.c_int32),
+        ("gamma_field", ctypes.c_int32),
         ("tau", ctypes.c_double), ("gamma", ctypes.c_double), ("g", ctypes.c_double),
         ("hstar", ctypes.c_double), ("delta", ctypes.c_double), ("ax", ctypes.c_double),
         ("ay", ctypes.c_double), ("theta0", ctypes.c_double), ("href", ctypes.c_double),
@@ -49,6 +50,7 @@ SIGNATURES = {
     "tflbm_workspace_bytes": (_sz, [_vp]),
     "tflbm_bind": (_int, [_vp, _vp, _sz]),
     "tflbm_init": (_int, [_vp, _dp, _dp, _vp]),
+    "tflbm_init_fields": (_int, [_vp, _dp, _dp, _dp, _vp]),
     "tflbm_step": (_int, [_vp, _i64, _vp]),
     "tflbm_step_count": (_i64, [_vp]),
     "tflbm_step_graphs": (_int, [_vp]),

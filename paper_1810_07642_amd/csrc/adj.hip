@@ -547,7 +547,7 @@ static AdjArgs make_adj_args(const tflbm_sim *s, void *d_adj, int ns = 1) {
   B.src = base + (s->adj_cur == 0 ? 0 : nb);
   B.dst = base + (s->adj_cur == 0 ? nb : 0);
   B.gk = (double *)(base + 2 * nb);
-  B.kfield = s->kfield ? (const void *)(s->ws + s->off_k) : nullptr;
+  B.kfield = s->kfield == kKappa ? (const void *)(s->ws + s->off_k) : nullptr;
   B.nx = s->p.nx;
   B.ny = s->p.ny;
   B.ldx = s->ldx;
@@ -585,6 +585,10 @@ size_t tflbm_adj_bytes(const tflbm_sim *sim) {
 int tflbm_adj_seed(tflbm_sim *sim, void *d_adj, const double *d_grad_h, tflbm_stream_t stream) {
   if (!sim || !d_adj || !d_grad_h || ((uintptr_t)d_adj & 255) != 0) return TFLBM_EINVAL;
   if (!sim->initialised) return TFLBM_ESTATE;
+  if (sim->kfield == kGammaKappa) {
+    sim->last_error = "the reverse pass does not take a position-dependent surface tension (params.gamma_field)";
+    return TFLBM_EINVAL;
+  }
   sim->adj_cur = 1;  // seed writes the "dst" of a cur=1 state, i.e. the first buffer
   AdjArgs B = make_adj_args(sim, d_adj);
   const int rc = hip_status(sim, launch_adj_seed(sim->p.prec, B, d_grad_h, (hipStream_t)stream));
@@ -599,7 +603,7 @@ int tflbm_adj_step(tflbm_sim *sim, void *d_adj, const void *d_capture_t, tflbm_s
   if (!sim->adj_seeded) return TFLBM_ESTATE;
   AdjArgs B = make_adj_args(sim, d_adj);
   B.cap = (const char *)d_capture_t;
-  const int rc = hip_status(sim, launch_adj_step(sim->p.prec, B, sim->kfield, 1, (hipStream_t)stream));
+  const int rc = hip_status(sim, launch_adj_step(sim->p.prec, B, sim->kfield == kKappa, 1, (hipStream_t)stream));
   if (rc) return rc;
   sim->adj_cur ^= 1;
   return TFLBM_OK;
@@ -617,7 +621,7 @@ int tflbm_adj_steps(tflbm_sim *sim, void *d_adj, const void *d_capture, int64_t 
     AdjArgs B = make_adj_args(sim, d_adj, ns);
     B.cap = cap + (size_t)t * cb;
     B.cap2 = ns == 2 ? cap + (size_t)(t - 1) * cb : nullptr;
-    const int rc = hip_status(sim, launch_adj_step(sim->p.prec, B, sim->kfield, ns, (hipStream_t)stream));
+    const int rc = hip_status(sim, launch_adj_step(sim->p.prec, B, sim->kfield == kKappa, ns, (hipStream_t)stream));
     if (rc) return rc;
     sim->adj_cur ^= 1;
     t -= ns;

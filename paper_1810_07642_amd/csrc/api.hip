@@ -106,8 +106,8 @@ void plan_launches(tflbm_sim *s) {
   // Reverse steps: at most two resident wavefronts per SIMD are planned for
   // (eight per CU).  At 4096^2 FP32 the one-step kernel, which fits three,
   // ran 9% faster with chunks sized for two than for three.
-  int aocc1 = adj_blocks_per_cu(s->p.prec, s->kfield, 1);
-  int aocc2 = adj_blocks_per_cu(s->p.prec, s->kfield, 2);
+  int aocc1 = adj_blocks_per_cu(s->p.prec, s->kfield == kKappa, 1);
+  int aocc2 = adj_blocks_per_cu(s->p.prec, s->kfield == kKappa, 2);
   aocc1 = aocc1 <= 0 || aocc1 > 8 ? 8 : aocc1;
   aocc2 = aocc2 <= 0 || aocc2 > 8 ? 8 : aocc2;
   s->adj_rows = choose_rows(ny, s->adj_nstrips, aocc1 * cus, kMinRowsAdj, "TFLBM_ADJ_ROWS");
@@ -223,6 +223,7 @@ int tflbm_check_params(const tflbm_params *p) {
   if (nblk * record_bytes(p->prec) >= ((int64_t)1 << 31)) return TFLBM_EINVAL;
   if (p->n_exp < 1 || p->n_exp > 32 || p->m_exp < 1 || p->m_exp > 32 || p->n_exp == p->m_exp) return TFLBM_EINVAL;
   if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24) return TFLBM_EINVAL;
+  if (p->gamma_field != 0 && p->gamma_field != 1) return TFLBM_EINVAL;
   if (!is_fin(p->tau) || !(p->tau > 0.5)) return TFLBM_EINVAL;
   if (!is_fin(p->gamma) || p->gamma < 0) return TFLBM_EINVAL;
   if (!is_fin(p->g) || !is_fin(p->ax) || !is_fin(p->ay) || !is_fin(p->theta0)) return TFLBM_EINVAL;
@@ -247,7 +248,7 @@ int tflbm_create(const tflbm_params *p, tflbm_sim **out) {
   const size_t P = (size_t)s->plane;
   s->nblk = (p->nx + record_sites(p->prec) - 1) / record_sites(p->prec);
   s->pop_bytes = (size_t)p->ny * s->nblk * record_bytes(p->prec);
-  s->kf_bytes = (size_t)work_bytes(p->prec) * P;
+  s->kf_bytes = (size_t)work_bytes(p->prec) * P * (p->gamma_field ? 2 : 1);  // kappa, or (-gamma/6, -gamma kappa)
   s->n_partials = 1024;
   size_t o = 0;
   s->off_a = o; o = align_up(o + s->pop_bytes, 4096);
@@ -289,7 +290,13 @@ int tflbm_bind(tflbm_sim *sim, void *d_ws, size_t bytes) {
 }
 
 int tflbm_init(tflbm_sim *sim, const double *d_h0, const double *d_theta, tflbm_stream_t stream) {
+  return tflbm_init_fields(sim, d_h0, d_theta, nullptr, stream);
+}
+
+int tflbm_init_fields(tflbm_sim *sim, const double *d_h0, const double *d_theta, const double *d_gamma,
+                      tflbm_stream_t stream) {
   if (!sim || !d_h0) return TFLBM_EINVAL;
+  if (d_gamma && !sim->p.gamma_field) return TFLBM_EINVAL;
   if (!sim->ws) return TFLBM_ESTATE;
   hipStream_t st = (hipStream_t)stream;
   drop_graphs(sim);
@@ -298,12 +305,12 @@ int tflbm_init(tflbm_sim *sim, const double *d_h0, const double *d_theta, tflbm_
   int rc = scratch_on_current_device(sim, &scr);
   if (rc) return rc;
   sim->cur = 1;  // init writes into the "dst" of a cur=1 state, i.e. buffer A
-  sim->kfield = d_theta != nullptr;
+  sim->kfield = sim->p.gamma_field ? kGammaKappa : (d_theta != nullptr ? kKappa : kNoField);
   plan_launches(sim);
   StepArgs A = make_step_args(sim);
   rc = hip_status(sim, hipMemsetAsync(sim->ws + sim->off_flag, 0, 256, st));
   if (rc) return rc;
-  rc = hip_status(sim, launch_init(sim->p.prec, A, d_h0, d_theta, sim->kconst, st));
+  rc = hip_status(sim, launch_init(sim->p.prec, A, d_h0, d_theta, d_gamma, sim->kfield, sim->kconst, st));
   if (rc) return rc;
   sim->cur = 0;
   sim->steps = 0;

@@ -10,6 +10,11 @@ namespace tflbm {
 
 enum Prec { kF64 = 0, kF32 = 1, kF16S = 2 };
 
+// Per-site field the film pressure reads: none (uniform kappa0 and gamma),
+// kappa [ny][ldx], or, for a position-dependent surface tension, the pair
+// (-gamma/6, -gamma kappa) per site [ny][ldx][2] (p = -gamma (lap h + kappa phi)).
+enum FieldKind { kNoField = 0, kKappa = 1, kGammaKappa = 2 };
+
 // D2Q9 velocities, l = 0..8 counter-clockwise from +x; odd l on the axes,
 // even l on the diagonals (Sec. II, eq. "speeds").
 constexpr int kCx[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
@@ -97,7 +102,7 @@ template <int P> __host__ __device__ constexpr int pad_bytes(int g) {
 struct StepArgs {
   const char *src;        // population records at time t
   char *dst;              // population records at time t + 1
-  const void *kfield;     // kappa field [ny][ldx] in T, or nullptr for kappa0
+  const void *kfield;     // per-site field (FieldKind: kappa [ny][ldx] or pairs [ny][ldx][2] in T), or nullptr
   char *capture;          // h, jx, jy planes [3][ny][ldx] in T, or nullptr
   int *flag;              // status word: bit 0 set on h <= 0 or non-finite h
   int nx, ny, ldx;        // ldx: pitch of the plane arrays (kappa, capture)

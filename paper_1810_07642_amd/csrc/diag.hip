@@ -44,7 +44,7 @@ __device__ __forceinline__ double lap_s(const double (&a)[E][E], int i, int j) {
   return (4.0 * ax + dg - 20.0 * a[i][j]) * (1.0 / 6.0);
 }
 
-template <int P, bool KF>
+template <int P, int KF>
 __global__ __launch_bounds__(256) void terms_kernel(StepArgs A, double *partial) {
   __shared__ double sh[kDH][kDH], sjx[kDH][kDH], sjy[kDH][kDH];
   __shared__ double sp[kDP][kDP], sdv[kDP][kDP];
@@ -74,14 +74,21 @@ __global__ __launch_bounds__(256) void terms_kernel(StepArgs A, double *partial)
     // film pressure and div j on the tile plus ring 1
     for (int idx = tid; idx < kDP * kDP; idx += 256) {
       const int i = idx / kDP + 1, j = idx % kDP + 1;
-      double kap = A.kappa0;
-      if constexpr (KF) {
-        const int y = wrap(y0 - 2 + i, ny), x = wrap(x0 - 2 + j, nx);
-        kap = (double)((const typename Form<P>::T *)A.kfield)[(size_t)y * A.ldx + x];
-      }
       const double r = A.hstar / sh[i][j];
       const double phi = ipow(r, A.n_exp) - ipow(r, A.m_exp);
-      sp[i - 1][j - 1] = -A.gamma * (lap_s(sh, i, j) + kap * phi);
+      if constexpr (KF == kGammaKappa) {
+        // per-site (-gamma/6, -gamma kappa)
+        const int y = wrap(y0 - 2 + i, ny), x = wrap(x0 - 2 + j, nx);
+        const auto *pr = (const typename Form<P>::T *)A.kfield + 2 * ((size_t)y * A.ldx + x);
+        sp[i - 1][j - 1] = (double)pr[0] * (6.0 * lap_s(sh, i, j)) + (double)pr[1] * phi;
+      } else {
+        double kap = A.kappa0;
+        if constexpr (KF == kKappa) {
+          const int y = wrap(y0 - 2 + i, ny), x = wrap(x0 - 2 + j, nx);
+          kap = (double)((const typename Form<P>::T *)A.kfield)[(size_t)y * A.ldx + x];
+        }
+        sp[i - 1][j - 1] = -A.gamma * (lap_s(sh, i, j) + kap * phi);
+      }
       sdv[i - 1][j - 1] = dx_s(sjx, i, j) + dy_s(sjy, i, j);
     }
     __syncthreads();
@@ -153,10 +160,11 @@ __global__ __launch_bounds__(512) void terms_final_kernel(const double *partial,
 }
 
 template <int P>
-static void launch_terms_p(const StepArgs &A, bool kf, int nb, double *partial, hipStream_t s) {
+static void launch_terms_p(const StepArgs &A, int kf, int nb, double *partial, hipStream_t s) {
   const dim3 block(kDT, kDT);
-  if (kf) terms_kernel<P, true><<<nb, block, 0, s>>>(A, partial);
-  else terms_kernel<P, false><<<nb, block, 0, s>>>(A, partial);
+  if (kf == kGammaKappa) terms_kernel<P, kGammaKappa><<<nb, block, 0, s>>>(A, partial);
+  else if (kf == kKappa) terms_kernel<P, kKappa><<<nb, block, 0, s>>>(A, partial);
+  else terms_kernel<P, kNoField><<<nb, block, 0, s>>>(A, partial);
 }
 
 int terms_blocks(int nx, int ny, int max_blocks) {
@@ -164,7 +172,7 @@ int terms_blocks(int nx, int ny, int max_blocks) {
   return (int)(ntiles < max_blocks ? ntiles : max_blocks);
 }
 
-hipError_t launch_terms(int prec, const StepArgs &A, bool kf, double *partial, int nb, double *out, hipStream_t s) {
+hipError_t launch_terms(int prec, const StepArgs &A, int kf, double *partial, int nb, double *out, hipStream_t s) {
   switch (prec) {
     case kF64: launch_terms_p<kF64>(A, kf, nb, partial, s); break;
     case kF32: launch_terms_p<kF32>(A, kf, nb, partial, s); break;

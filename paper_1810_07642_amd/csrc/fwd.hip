@@ -134,12 +134,33 @@ __device__ __forceinline__ void load_row(rsrc_t row, const Lane<kF32> &L, unsign
   }
 }
 
-// Kappa at the lane's columns of one row of the kappa field (resource krow),
-// in flight as the rows are: one 64-bit word (two FP32 columns, column 0 in
-// the low half) or one FP64 value; kappa_cols splits it into columns.
-template <int P> using KapBuf = std::conditional_t<Form<P>::V == 2, unsigned long long, double>;
-template <int P> __device__ __forceinline__ void load_kappa(rsrc_t krow, const Lane<P> &L, KapBuf<P> &out) {
-  if constexpr (Form<P>::V == 2) {
+// Per-site field of the film pressure (field kind KF):
+//   kNoField: none (uniform kappa0 and gamma);
+//   kKappa: kappa [ny][ldx] in T;
+//   kGammaKappa: the pair (a, b) = (-gamma/6, -gamma kappa) per site, [ny][ldx][2]
+//   in T, for a position-dependent surface tension (p = a 6 lap h + b phi(h)).
+// The values of a lane's columns of one row travel with the rows: FP32 kappa
+// as one 64-bit word (two columns, column 0 in the low half), FP32 pairs as
+// one 128-bit word (a0 b0 a1 b1), FP64 kappa as one double, FP64 pairs as one
+// 128-bit word (a, b); kappa_cols splits them into columns.
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+template <int P, int KF>
+using KapBuf = std::conditional_t<KF == kGammaKappa, u32x4v,
+                                  std::conditional_t<Form<P>::V == 2, unsigned long long, double>>;
+template <int P, int KF> __device__ __forceinline__ void load_kappa(rsrc_t krow, const Lane<P> &L, KapBuf<P, KF> &out) {
+  if constexpr (KF == kGammaKappa) {
+    if constexpr (Form<P>::V == 2) {
+      if (L.allvecp || L.vecp) {
+        out = __builtin_bit_cast(u32x4v, __builtin_amdgcn_raw_buffer_load_b128(krow, L.col[0] * 8, 0, kLoadPolicy));
+      } else {
+        const u32x2 w0 = __builtin_amdgcn_raw_buffer_load_b64(krow, L.col[0] * 8, 0, kLoadPolicy);
+        const u32x2 w1 = __builtin_amdgcn_raw_buffer_load_b64(krow, L.col[1] * 8, 0, kLoadPolicy);
+        out = u32x4v{w0.x, w0.y, w1.x, w1.y};
+      }
+    } else {
+      out = __builtin_bit_cast(u32x4v, __builtin_amdgcn_raw_buffer_load_b128(krow, L.col[0] * 16, 0, kLoadPolicy));
+    }
+  } else if constexpr (Form<P>::V == 2) {
     if (L.allvecp || L.vecp) {
       out = __builtin_bit_cast(unsigned long long, __builtin_amdgcn_raw_buffer_load_b64(krow, L.col[0] * 4, 0, kLoadPolicy));
     } else {
@@ -151,9 +172,22 @@ template <int P> __device__ __forceinline__ void load_kappa(rsrc_t krow, const L
     out = ld_f64(krow, L.col[0] * 8);
   }
 }
-template <int P>
-__device__ __forceinline__ void kappa_cols(const KapBuf<P> &k, typename Form<P>::T (&out)[Form<P>::V]) {
-  if constexpr (Form<P>::V == 2) {
+// Splits a row's field values into the kappa slot k (kappa, or b = -gamma
+// kappa) and, for kGammaKappa, a = -gamma/6.
+template <int P, int KF>
+__device__ __forceinline__ void kappa_cols(const KapBuf<P, KF> &k, typename Form<P>::T (&out)[Form<P>::V],
+                                           typename Form<P>::T (&aco)[Form<P>::V]) {
+  if constexpr (KF == kGammaKappa) {
+    if constexpr (Form<P>::V == 2) {
+      aco[0] = __uint_as_float(k.x);
+      out[0] = __uint_as_float(k.y);
+      aco[1] = __uint_as_float(k.z);
+      out[1] = __uint_as_float(k.w);
+    } else {
+      aco[0] = __longlong_as_double(((long long)k.y << 32) | k.x);
+      out[0] = __longlong_as_double(((long long)k.w << 32) | k.z);
+    }
+  } else if constexpr (Form<P>::V == 2) {
     const u32x2 w = __builtin_bit_cast(u32x2, k);
     out[0] = __uint_as_float(w.x);
     out[1] = __uint_as_float(w.y);
@@ -216,7 +250,7 @@ __device__ __forceinline__ void shift_x(int l, const T *in, T *out) {
 // has zero momentum and is a fixed point of the collision at rest, so the
 // step on d is the step on f; only small changes of a film near href keep
 // more significant digits.
-template <int P, bool KF> struct Stage {
+template <int P, int KF> struct Stage {
   using T = typename Form<P>::T;
   static constexpr int V = Form<P>::V;
   T h0[V + 2], h1[V + 2], h2[V + 2];  // dh of rows r, r-1, r-2 with the left/right neighbours
@@ -224,12 +258,14 @@ template <int P, bool KF> struct Stage {
   // cA p(x) + cD (p(x-1) + p(x+1)), of rows r-1, r-2, r-3
   T dx1[V], dx2[V], dx3[V];
   T sm1[V], sm2[V], sm3[V];
-  T kn[V], kr[V];                     // kappa of rows r and r-1
+  T kn[V], kr[V];                     // kappa (or -gamma kappa) of rows r and r-1
+  T an[V], ar[V];                     // -gamma/6 of rows r and r-1 (kGammaKappa)
   T (*hist)[9][64 * V];
 
-  // kap: kappa of row r (loaded with the row, load_kappa; unused without a
-  // kappa field)
-  __device__ __forceinline__ void ingest(int k, const T (&f)[9][V], const T (&kap)[V], T (&f2)[9][V], int lane) {
+  // kap, aco: the field values of row r (loaded with the row, load_kappa;
+  // unused without a field)
+  __device__ __forceinline__ void ingest(int k, const T (&f)[9][V], const T (&kap)[V], const T (&aco)[V],
+                                         T (&f2)[9][V], int lane) {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       T hs = f[0][v];
@@ -243,7 +279,11 @@ template <int P, bool KF> struct Stage {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       kr[v] = kn[v];
-      if constexpr (KF) kn[v] = kap[v];
+      if constexpr (KF != kNoField) kn[v] = kap[v];
+      if constexpr (KF == kGammaKappa) {
+        ar[v] = an[v];
+        an[v] = aco[v];
+      }
     }
     // row r-2 leaves the LDS slot that row r takes over
     const int slot = k & 1;
@@ -278,8 +318,14 @@ template <int P, bool KF> struct Stage {
         // 6 lap h = 6 lap dh = 4 sum_axes + sum_diagonals - 20 dh
         const T lap6 = madd(T(-20), h1[v + 1], madd(T(4), odd, even));
         const T phi = disjoining(C.hstar * recip(hc), C.n_exp, C.m_exp);
-        const T kap = KF ? kr[v] : C.kap0;
-        pc[v + 1] = madd(C.mgam6, lap6, C.mgam * kap * phi);
+        if constexpr (KF == kGammaKappa) {
+          // per-site (-gamma/6, -gamma kappa), rounded at init as the scalar
+          // path rounds (-gamma/6) and (-gamma) kappa
+          pc[v + 1] = madd(ar[v], lap6, kr[v] * phi);
+        } else {
+          const T kap = KF == kKappa ? kr[v] : C.kap0;
+          pc[v + 1] = madd(C.mgam6, lap6, C.mgam * kap * phi);
+        }
       }
       pc[0] = from_left(pc[V]);
       pc[V + 1] = from_right(pc[1]);
@@ -609,7 +655,7 @@ __device__ __forceinline__ void capture_row(const StepArgs &A, char *base, int q
 // step t at A.capture, step t + 1 one capture block later.
 // G0 (FP16S only): the launch has g = 0, so the rest equilibrium of the
 // FP16S shift has no moving part and its code is left out.
-template <int P, bool KF, bool CAP, int NS, bool G0 = false>
+template <int P, int KF, bool CAP, int NS, bool G0 = false>
 __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   using T = typename Form<P>::T;
   constexpr int V = Form<P>::V;
@@ -694,10 +740,10 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   // kappa travels with the rows: ka and kb hold the kappa of the rows in fa
   // and fb, and stage 1, three rows behind stage 0, takes it from kq (the
   // kappa of stage 0's last three rows)
-  const uint32_t kpitch = (uint32_t)(A.ldx * sizeof(T));
+  const uint32_t kpitch = (uint32_t)(A.ldx * sizeof(T) * (KF == kGammaKappa ? 2 : 1));
   auto rsrc_kap = [&](int row) { return make_rsrc((const char *)A.kfield + (size_t)row * kpitch, kpitch); };
-  KapBuf<P> ka, kb;
-  T kq[3][V];
+  KapBuf<P, KF> ka, kb;
+  T kq[3][V], aq[3][V];
   using RowBuf = std::conditional_t<P == kF32, unsigned long long[9], T[9][V]>;
   RowBuf fa, fb;  // stored values of rows r (being consumed) and r + 1
   auto load_buf = [&](rsrc_t row, RowBuf &out) {
@@ -705,11 +751,11 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
     else load_row<P>(row, L, out, A);
   };
   load_buf(rsrc_src(ry), fa);
-  if constexpr (KF) load_kappa<P>(rsrc_kap(ry), L, ka);
+  if constexpr (KF != kNoField) load_kappa<P, KF>(rsrc_kap(ry), L, ka);
   if (KL > 1) {
     const int r1 = ry + 1 == ny ? 0 : ry + 1;
     load_buf(rsrc_src(r1), fb);
-    if constexpr (KF) load_kappa<P>(rsrc_kap(r1), L, kb);
+    if constexpr (KF != kNoField) load_kappa<P, KF>(rsrc_kap(r1), L, kb);
   }
   if constexpr (P == kF16S) {
     // the c_ly = +1 values of the first row, which fp16s_decode otherwise
@@ -720,7 +766,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
       for (int i = 0; i < 3; ++i) cn[i][v] = unpack16(fa[2 + i][0], v, A.qinv);
   }
 
-  auto iteration = [&](int k, RowBuf &cur, const RowBuf &nxt, KapBuf<P> &kcur) {
+  auto iteration = [&](int k, RowBuf &cur, const RowBuf &nxt, KapBuf<P, KF> &kcur) {
     T f[9][V], f2[9][V];
     if constexpr (P == kF32) {
 #pragma unroll
@@ -738,15 +784,15 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
 #pragma unroll
       for (int l = 0; l < 9; ++l) shift_x<T, V>(l, cur[l], f[l]);
     }
-    T k0[V];
-    if constexpr (KF) kappa_cols<P>(kcur, k0);
-    S0.ingest(k, f, k0, f2, lane);
+    T k0[V], a0[V];
+    if constexpr (KF != kNoField) kappa_cols<P, KF>(kcur, k0, a0);
+    S0.ingest(k, f, k0, a0, f2, lane);
     // prefetch row r + 2 into the registers just freed.  Past the tile's last
     // row the loads go to an empty buffer range (no memory access, zeros):
     // every iteration issues the same loads, so the compiler's waits for a
     // row need not drain the loads of the rows after it.
     load_buf(k + 2 < KL ? rsrc_src(rpre) : make_rsrc(A.src, 0), cur);
-    if constexpr (KF) load_kappa<P>(k + 2 < KL ? rsrc_kap(rpre) : make_rsrc(A.kfield, 0), L, kcur);
+    if constexpr (KF != kNoField) load_kappa<P, KF>(k + 2 < KL ? rsrc_kap(rpre) : make_rsrc(A.kfield, 0), L, kcur);
     T post[9][V], hv[V], jxv[V], jyv[V];
     if (S0.finish(k, f2, post, hv, jxv, jyv, C, L, bad)) {
       const int q = y0 - HALO + k - 2;  // row of the post-collision values (unwrapped)
@@ -786,7 +832,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
         if (e >= 2) {
           const int j = e - 2;  // stage 1 row index; its row is q - 1 = y0 - 2 + j
           T g2[9][V];
-          S1.ingest(j, g, kq[2], g2, lane);
+          S1.ingest(j, g, kq[2], aq[2], g2, lane);
           T post2[9][V], hv2[V], jx2[V], jy2[V];
           if (S1.finish(j, g2, post2, hv2, jx2, jy2, C, L, bad)) {
             store_row<P, G0>(A, y0 - 4 + j, post2, hv2, L, x0, xend, lane);
@@ -797,12 +843,17 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
         }
       }
     }
-    if constexpr (KF && NS == 2) {
+    if constexpr (KF != kNoField && NS == 2) {
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         kq[2][v] = kq[1][v];
         kq[1][v] = kq[0][v];
         kq[0][v] = k0[v];
+        if constexpr (KF == kGammaKappa) {
+          aq[2][v] = aq[1][v];
+          aq[1][v] = aq[0][v];
+          aq[0][v] = a0[v];
+        }
       }
     }
     ry = ry + 1 == ny ? 0 : ry + 1;
@@ -836,7 +887,8 @@ template <int P> __device__ __forceinline__ char *pop_ptr(char *buf, int l, int 
 }
 
 template <int P>
-__global__ void init_kernel(StepArgs A, const double *h0, const double *theta, double kconst) {
+__global__ void init_kernel(StepArgs A, const double *h0, const double *theta, const double *gamma, int field,
+                            double kconst) {
   using T = typename Form<P>::T;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
@@ -874,9 +926,19 @@ __global__ void init_kernel(StepArgs A, const double *h0, const double *theta, d
       *(__half *)pop_ptr<P>(A.dst, l, y, wrap(x - kCx[l], A.nx), A) = dq;
     }
   }
-  if (theta != nullptr) {
+  if (field == kKappa) {
     const double th = theta[(size_t)y * A.nx + x];
     ((T *)A.kfield)[(size_t)y * A.ldx + x] = (T)((1.0 - cos(th)) * kconst);
+  } else if (field == kGammaKappa) {
+    // (a, b) = (-gamma/6, -gamma kappa), each rounded to T as the scalar path
+    // rounds its constants (-gamma/6) and (-gamma) and the product of (-gamma)
+    // with kappa in T: a uniform field steps bit for bit like the scalar path
+    const double gm = gamma != nullptr ? gamma[(size_t)y * A.nx + x] : A.gamma;
+    if (!(gm >= 0.0 && gm < INFINITY)) atomicOr(A.flag, 1);
+    const T kap = theta != nullptr ? (T)((1.0 - cos(theta[(size_t)y * A.nx + x])) * kconst) : (T)A.kappa0;
+    T *pr = (T *)A.kfield + 2 * ((size_t)y * A.ldx + x);
+    pr[0] = (T)(-gm / 6.0);
+    pr[1] = (T)(-gm) * kap;
   }
 }
 
@@ -980,20 +1042,22 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s) 
 }
 
 // ---- launchers -----------------------------------------------------------------
-template <int P, int NS, bool G0>
-static void launch_step_v(const StepArgs &A, bool kf, bool cap, hipStream_t s) {
+template <int P, int NS, bool G0, int KF>
+static void launch_step_k(const StepArgs &A, bool cap, hipStream_t s) {
   const dim3 grid(8 * A.per_xcd), block(64);
-  if (kf) {
-    if (cap) step_kernel<P, true, true, NS, G0><<<grid, block, 0, s>>>(A);
-    else step_kernel<P, true, false, NS, G0><<<grid, block, 0, s>>>(A);
-  } else {
-    if (cap) step_kernel<P, false, true, NS, G0><<<grid, block, 0, s>>>(A);
-    else step_kernel<P, false, false, NS, G0><<<grid, block, 0, s>>>(A);
-  }
+  if (cap) step_kernel<P, KF, true, NS, G0><<<grid, block, 0, s>>>(A);
+  else step_kernel<P, KF, false, NS, G0><<<grid, block, 0, s>>>(A);
+}
+
+template <int P, int NS, bool G0>
+static void launch_step_v(const StepArgs &A, int kf, bool cap, hipStream_t s) {
+  if (kf == kGammaKappa) launch_step_k<P, NS, G0, kGammaKappa>(A, cap, s);
+  else if (kf == kKappa) launch_step_k<P, NS, G0, kKappa>(A, cap, s);
+  else launch_step_k<P, NS, G0, kNoField>(A, cap, s);
 }
 
 template <int P, int NS>
-static hipError_t launch_step_p(const StepArgs &A, bool kf, bool cap, hipStream_t s) {
+static hipError_t launch_step_p(const StepArgs &A, int kf, bool cap, hipStream_t s) {
   if constexpr (P == kF16S) {
     if (A.g == 0.0) {
       launch_step_v<P, NS, true>(A, kf, cap, s);
@@ -1004,7 +1068,7 @@ static hipError_t launch_step_p(const StepArgs &A, bool kf, bool cap, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_step(int prec, const StepArgs &A, bool kf, bool cap, hipStream_t s) {
+hipError_t launch_step(int prec, const StepArgs &A, int kf, bool cap, hipStream_t s) {
   switch (prec) {
     case kF64: return launch_step_p<kF64, 1>(A, kf, cap, s);
     case kF32: return launch_step_p<kF32, 1>(A, kf, cap, s);
@@ -1012,7 +1076,7 @@ hipError_t launch_step(int prec, const StepArgs &A, bool kf, bool cap, hipStream
   }
 }
 
-hipError_t launch_step2(int prec, const StepArgs &A, bool kf, bool cap, hipStream_t s) {
+hipError_t launch_step2(int prec, const StepArgs &A, int kf, bool cap, hipStream_t s) {
   switch (prec) {
     case kF64: return launch_step_p<kF64, 2>(A, kf, cap, s);
     case kF32: return launch_step_p<kF32, 2>(A, kf, cap, s);
@@ -1021,22 +1085,24 @@ hipError_t launch_step2(int prec, const StepArgs &A, bool kf, bool cap, hipStrea
 }
 
 template <int P, int NS, bool G0>
-static int occupancy_v(bool kf) {
+static int occupancy_v(int kf) {
   int n = 0;
-  const hipError_t e = kf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, true, false, NS, G0>, 64, 0)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, false, false, NS, G0>, 64, 0);
+  const hipError_t e =
+      kf == kGammaKappa ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, kGammaKappa, false, NS, G0>, 64, 0)
+      : kf == kKappa    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, kKappa, false, NS, G0>, 64, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, kNoField, false, NS, G0>, 64, 0);
   return e == hipSuccess ? n : 0;
 }
 
 template <int P>
-static int occupancy_p(bool kf, int ns, bool g0) {
+static int occupancy_p(int kf, int ns, bool g0) {
   if constexpr (P == kF16S) {
     if (g0) return ns == 2 ? occupancy_v<P, 2, true>(kf) : occupancy_v<P, 1, true>(kf);
   }
   return ns == 2 ? occupancy_v<P, 2, false>(kf) : occupancy_v<P, 1, false>(kf);
 }
 
-int step_blocks_per_cu(int prec, bool kf, int ns, bool g0) {
+int step_blocks_per_cu(int prec, int kf, int ns, bool g0) {
   switch (prec) {
     case kF64: return occupancy_p<kF64>(kf, ns, g0);
     case kF32: return occupancy_p<kF32>(kf, ns, g0);
@@ -1052,13 +1118,13 @@ int record_bytes(int prec) {
   return prec == kF64 ? Form<kF64>::RB : (prec == kF32 ? Form<kF32>::RB : Form<kF16S>::RB);
 }
 
-hipError_t launch_init(int prec, const StepArgs &A, const double *h0, const double *theta, double kconst,
-                       hipStream_t s) {
+hipError_t launch_init(int prec, const StepArgs &A, const double *h0, const double *theta, const double *gamma,
+                       int field, double kconst, hipStream_t s) {
   const dim3 block(256), grid((A.nx + 255) / 256, A.ny);
   switch (prec) {
-    case kF64: init_kernel<kF64><<<grid, block, 0, s>>>(A, h0, theta, kconst); break;
-    case kF32: init_kernel<kF32><<<grid, block, 0, s>>>(A, h0, theta, kconst); break;
-    default: init_kernel<kF16S><<<grid, block, 0, s>>>(A, h0, theta, kconst); break;
+    case kF64: init_kernel<kF64><<<grid, block, 0, s>>>(A, h0, theta, gamma, field, kconst); break;
+    case kF32: init_kernel<kF32><<<grid, block, 0, s>>>(A, h0, theta, gamma, field, kconst); break;
+    default: init_kernel<kF16S><<<grid, block, 0, s>>>(A, h0, theta, gamma, field, kconst); break;
   }
   return hipGetLastError();
 }

@@ -17,7 +17,7 @@ struct tflbm_sim {
   int n_partials = 0;
   char *ws = nullptr;     // bound device workspace
   bool initialised = false;
-  bool kfield = false;    // kappa read per site (theta field given at init)
+  int kfield = 0;         // FieldKind: kappa (theta field given at init) or the gamma-kappa pairs read per site
   int cur = 0;            // 0: buffer A holds the current populations
   int64_t steps = 0;
   double kconst = 0.0;    // (n - 1)(m - 1)/((n - m) h_*)

@@ -270,7 +270,7 @@ def main(argv=None):
         text = traffic_summary(
             f"HBM traffic of the {args.storage.upper()} step kernel, patterned dewetting 4096 x 4096",
             f"{args.storage.upper()} storage, kappa field, 2 time steps per launch",
-            rf"step_kernel<{STEP_KERNEL_PREC[args.storage]}, true, false, 2,", args.fetch, args.write,
+            rf"step_kernel<{STEP_KERNEL_PREC[args.storage]}, 1, false, 2,", args.fetch, args.write,
             r * N4096, w * N4096, 2, STEP_SOURCES, cmds, sq_dir=args.sq, trace_dir=args.trace,
             alg_desc=f"records read and written once and the kappa field read once ({r}/{w} B/site)",
             notes=["`bench.py --profile-steps 20` runs 20 steps (10 launches) of the benchmark workload, "

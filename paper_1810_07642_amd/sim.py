@@ -13,7 +13,7 @@ import torch
 from . import _lib
 
 PARAM_KEYS = ("tau", "gamma", "g", "hstar", "n", "m", "delta", "ax", "ay", "theta0",
-              "href", "fp16_scale_log2")
+              "href", "fp16_scale_log2", "gamma_field")
 
 
 def _stream(device):
@@ -64,6 +64,8 @@ def make_params(nx, ny, prec="fp64", **kw):
             p.m_exp = int(v)
         elif k == "fp16_scale_log2":
             p.fp16_scale_log2 = int(v)
+        elif k == "gamma_field":
+            p.gamma_field = int(bool(v))
         else:
             setattr(p, k, float(v))
     return p
@@ -123,12 +125,16 @@ class Sim:
     def _chk(self, code, where):
         return _lib.check(code, where, self.h)
 
-    def init(self, h0, theta=None):
-        """f = E(h0); kappa from theta ([ny, nx] float64) or the uniform theta0."""
+    def init(self, h0, theta=None, gamma=None):
+        """f = E(h0); kappa from theta ([ny, nx] float64) or the uniform theta0;
+        gamma: a per-site surface tension field (the handle must be created
+        with gamma_field=True), else the scalar gamma."""
         shape = (self.ny, self.nx)
         self.h0 = _dev_f64(h0, self.device, shape, "h0")
         self.theta = _dev_f64(theta, self.device, shape, "theta")
-        self._chk(self.lib.tflbm_init(self.h, _addr(self.h0), _addr(self.theta), self.stream), "tflbm_init")
+        self.gamma = _dev_f64(gamma, self.device, shape, "gamma")
+        self._chk(self.lib.tflbm_init_fields(self.h, _addr(self.h0), _addr(self.theta), _addr(self.gamma),
+                                             self.stream), "tflbm_init_fields")
         return self
 
     def step(self, nsteps=1):

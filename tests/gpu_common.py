@@ -123,6 +123,22 @@ OBSERVED = {
     "smallamp64x2000.fp32.href1": 3.399e-06,
     "spreading512x200.fp16s.href0.5": 1.390e-06,
     "spreading512x200.fp32.href0.5": 1.234e-05,
+    "gamma.case0.fuse1.fp16s": 1.339e-05,
+    "gamma.case0.fuse1.fp32": 1.109e-06,
+    "gamma.case0.fuse2.fp16s": 1.339e-05,
+    "gamma.case0.fuse2.fp32": 1.109e-06,
+    "gamma.case1.fuse1.fp16s": 4.913e-06,
+    "gamma.case1.fuse1.fp32": 8.085e-07,
+    "gamma.case1.fuse2.fp16s": 4.913e-06,
+    "gamma.case1.fuse2.fp32": 8.085e-07,
+    "gamma.case2.fuse1.fp16s": 6.833e-06,
+    "gamma.case2.fuse1.fp32": 7.682e-07,
+    "gamma.case2.fuse2.fp16s": 6.833e-06,
+    "gamma.case2.fuse2.fp32": 7.682e-07,
+    "gamma.case3.fuse1.fp16s": 1.103e-06,
+    "gamma.case3.fuse1.fp32": 4.021e-07,
+    "gamma.case3.fuse2.fp16s": 1.103e-06,
+    "gamma.case3.fuse2.fp32": 4.021e-07,
 }
 
 

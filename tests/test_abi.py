@@ -37,8 +37,8 @@ def test_version_and_strerror(lib):
 
 
 def test_struct_layout_matches_header(lib):
-    # six int32 then nine doubles, natural alignment
-    assert ctypes.sizeof(_lib.Params) == 6 * 4 + 9 * 8
+    # seven int32, padding to 8 bytes, then nine doubles (natural alignment)
+    assert ctypes.sizeof(_lib.Params) == 7 * 4 + 4 + 9 * 8
     p = params(lib)
     assert (p.n_exp, p.m_exp, p.tau, p.gamma, p.hstar, p.delta) == (9, 3, 1.0, 0.01, 0.05, 1.0)
     assert p.fp16_scale_log2 == 12
@@ -47,7 +47,7 @@ def test_struct_layout_matches_header(lib):
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("ny", -3), ("prec", 3), ("tau", 0.5), ("tau", float("nan")), ("hstar", 0.0),
     ("gamma", -1.0), ("delta", -0.1), ("n_exp", 3), ("m_exp", 0), ("fp16_scale_log2", 30),
-    ("g", float("inf")), ("href", -1.0),
+    ("g", float("inf")), ("href", -1.0), ("gamma_field", 2),
 ])
 def test_invalid_parameters_rejected(lib, field, value):
     p = params(lib, **{field: value})
@@ -122,4 +122,21 @@ def test_call_order_and_null_pointers(lib):
     assert lib.tflbm_adj_steps(h, ctypes.c_void_p(256), None, 2, None) == _lib.TFLBM_EINVAL
     assert lib.tflbm_step_count(h) == 0
     assert lib.tflbm_step_count(None) == -1
+    lib.tflbm_destroy(h)
+
+
+def test_gamma_field_needs_the_flag(lib):
+    """tflbm_init_fields with a surface tension field on a handle created
+    without params.gamma_field is refused before any device work; with the
+    flag the workspace holds two values per site instead of one."""
+    p = params(lib, nx=100, ny=30)
+    h = ctypes.c_void_p()
+    assert lib.tflbm_create(ctypes.byref(p), ctypes.byref(h)) == _lib.TFLBM_OK
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.tflbm_init_fields(h, fake, None, fake, None) == _lib.TFLBM_EINVAL
+    ws0 = lib.tflbm_workspace_bytes(h)
+    lib.tflbm_destroy(h)
+    p.gamma_field = 1
+    assert lib.tflbm_create(ctypes.byref(p), ctypes.byref(h)) == _lib.TFLBM_OK
+    assert lib.tflbm_workspace_bytes(h) > ws0
     lib.tflbm_destroy(h)

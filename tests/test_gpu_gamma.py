@@ -1,0 +1,198 @@
+"""Position-dependent surface tension gamma(x) (Sec. II: the sentence after eq.
+"n_laplace" names such a field among those the stencils act on): the film
+pressure p = -gamma(x) (lap h + kappa f(h)) and F_film = -h grad p, through
+tflbm_init_fields, against the FP64 oracle (oracle.lbm with its gam argument).
+
+FP64: max |dh| / max h <= 1e-12.  FP32 and FP16S: check_err (a-priori bound
+and 10 x the observed error).  A uniform field is the scalar path bit for bit
+in every form; fused and single steps agree bit for bit; the field enters the
+term-balance diagnostic; the reverse pass refuses such a handle."""
+import ctypes
+import math
+import os
+
+import pytest
+import torch
+
+from gpu_common import banner, check_err, fp16s_tol, fp32_tol, max_rel, random_case
+from oracle import diag, lbm, local
+from paper_1810_07642_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def gamma_field(ny, nx, seed, lo=0.005, hi=0.02):
+    g = torch.Generator().manual_seed(seed)
+    return lo + (hi - lo) * torch.rand((ny, nx), generator=g, dtype=torch.float64)
+
+
+def oracle_gamma_run(p, h0, th, gam, steps):
+    P = lbm.Params(**p)
+    f = lbm.run(lbm.init(h0, P), lbm.kappa(th, P), P, steps, gam)
+    h, ux, uy = lbm.readout(f)
+    return h, ux, uy, lbm.mass(f), float(f[1:].abs().max())
+
+
+def gpu_gamma_run(p, h0, th, gam, steps, prec, fuse=None, **extra):
+    from paper_1810_07642_amd import Sim
+    ny, nx = h0.shape
+    if fuse is not None:
+        os.environ["TFLBM_FUSE"] = fuse
+    try:
+        sim = Sim(nx, ny, prec, gamma_field=True, **dict(p, **extra)).init(h0, th, gam)
+    finally:
+        os.environ.pop("TFLBM_FUSE", None)
+    sim.step(steps)
+    sim.check()
+    h, ux, uy = (t.cpu() for t in sim.read())
+    return h, ux, uy, sim.mass(), sim
+
+
+CASES = [
+    # ny, nx, steps, params, theta field
+    (70, 150, 120, dict(tau=0.8, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5, ay=-2e-5), True),
+    (23, 37, 90, dict(tau=1.0, g=0.0, hstar=0.2, delta=0.7), False),
+    (130, 97, 60, dict(tau=1.3, g=-2e-4, hstar=0.15, delta=1.5, ax=-3e-5, n=4, m=3), True),
+    (3, 2, 30, dict(tau=0.9, g=1e-3, hstar=0.1, delta=1.0, ay=1e-5), True),
+]
+
+
+@pytest.mark.parametrize("fuse", ["1", "2"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_gamma_field_matches_oracle(case, fuse):
+    ny, nx, steps, p, field = CASES[case]
+    banner(f"gamma field case {case}: {ny}x{nx}, {steps} steps, steps per pass {fuse}")
+    h0, th = random_case(ny, nx, 500 + case)
+    if not field:
+        th = torch.full_like(h0, 0.45)
+    gam = gamma_field(ny, nx, 600 + case)
+    ho, uxo, uyo, mo, fmov = oracle_gamma_run(p, h0, th, gam, steps)
+    hmax = float(ho.abs().max())
+    for prec, extra in (("fp64", {}), ("fp32", {"href": 0.45}), ("fp16s", {"href": 0.45, "fp16_scale_log2": 14})):
+        kw = dict(extra)
+        if not field:
+            kw["theta0"] = 0.45
+        hg, uxg, uyg, mg, sim = gpu_gamma_run(p, h0, th if field else None, gam, steps, prec, fuse, **kw)
+        err = max_rel(hg, ho)
+        if prec == "fp64":
+            print(f"OBS gamma.case{case}.fuse{fuse}.fp64 {err:.3e}", flush=True)
+            assert err <= TOL64
+            assert max_rel(uxg, uxo) <= 10 * TOL64 or float((uxg - uxo).abs().max()) < 1e-18
+            assert max_rel(uyg, uyo) <= 10 * TOL64 or float((uyg - uyo).abs().max()) < 1e-18
+            assert abs(mg - mo) <= 1e-13 * abs(mo)
+        else:
+            apriori = fp32_tol(steps) if prec == "fp32" else fp16s_tol(steps, fmov / hmax)
+            check_err(f"gamma.case{case}.fuse{fuse}.{prec}", err, apriori)
+        del sim
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_uniform_gamma_field_is_the_scalar_path_bitwise(prec):
+    """A field equal to params.gamma everywhere, given explicitly or as NULL,
+    steps bit for bit like a handle without the field: the pair (-gamma/6,
+    -gamma kappa) is rounded at init as the scalar path rounds its constants;
+    with and without a theta field, fused pairs and a single step."""
+    from paper_1810_07642_amd import Sim
+    p = dict(tau=0.9, gamma=0.013, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5, ay=-1e-5)
+    if prec != "fp64":
+        p["href"] = 0.45
+    for (ny, nx, field) in [(70, 150, True), (23, 37, False), (130, 300, True)]:
+        h0, th = random_case(ny, nx, 51)
+        thf = th if field else None
+        kw = dict(p) if field else dict(p, theta0=0.5)
+        ref = Sim(nx, ny, prec, **kw).init(h0, thf)
+        a = Sim(nx, ny, prec, gamma_field=True, **kw).init(h0, thf, torch.full_like(h0, 0.013))
+        b = Sim(nx, ny, prec, gamma_field=True, **kw).init(h0, thf)
+        for s in (ref, a, b):
+            s.step(7)
+            s.check()
+        st = ref.state_save().cpu()
+        assert torch.equal(a.state_save().cpu(), st), (prec, ny, nx)
+        assert torch.equal(b.state_save().cpu(), st), (prec, ny, nx)
+
+
+def test_gamma_field_fused_equals_single_steps_bitwise():
+    """Two fused steps per pass give the bits of two single passes with the
+    pair field too (the second stage takes the field from the register queue
+    of the first), in every form, on ragged and odd grids."""
+    from paper_1810_07642_amd import Sim
+    p = dict(tau=0.9, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5, ay=-1e-5)
+    for prec in ("fp64", "fp32", "fp16s"):
+        for (ny, nx) in [(70, 150), (23, 37), (6, 300), (130, 97)]:
+            h0, th = random_case(ny, nx, 52)
+            gam = gamma_field(ny, nx, 53)
+            kw = dict(p) if prec == "fp64" else dict(p, href=0.45)
+            out = []
+            for fuse in ("2", "1"):
+                h, ux, uy, m, sim = gpu_gamma_run(kw, h0, th, gam, 7, prec, fuse)
+                out.append((sim.state_save().cpu(), h))
+                del sim
+            assert torch.equal(out[0][0], out[1][0]), (prec, ny, nx)
+            assert torch.equal(out[0][1], out[1][1]), (prec, ny, nx)
+
+
+def test_gamma_field_full_size_sampled_sites():
+    """The 4096^2 dewetting workload with a surface tension varying in stripes
+    across the contact-angle stripes (0.01 (1 + 0.5 sin(2 pi y / 512))), in the
+    benchmark's launch shape, 4 steps: FP64 against the oracle's periodic
+    windows at 40 seeded sites and the corners."""
+    banner("4096^2 dewetting with a gamma field, sampled sites")
+    p, h0, th = inputs.patterned_dewetting()
+    y = torch.arange(4096, dtype=torch.float64).view(-1, 1)
+    gam = (0.01 * (1.0 + 0.5 * torch.sin(2 * math.pi * y / 512.0))).expand(4096, 4096).contiguous()
+    steps = 4
+    sites = inputs.random_pixels(4096, 4096, 40, seed=14) + [(0, 0), (4095, 4095), (0, 4095), (4095, 0)]
+    hs, _, _ = local.sampled_run(h0, th, lbm.Params(**p), steps, sites, gam)
+    ys = torch.tensor([s[0] for s in sites])
+    xs = torch.tensor([s[1] for s in sites])
+    hg, _, _, _, sim = gpu_gamma_run(p, h0, th, gam, steps, "fp64")
+    err = max_rel(hg[ys, xs], hs)
+    print(f"OBS gamma.sampled4096x4.fp64 {err:.3e}", flush=True)
+    assert err <= TOL64
+    del sim, hg
+    torch.cuda.empty_cache()
+
+
+def test_gamma_field_term_norms_match_oracle():
+    """The term-balance diagnostic reads the pair field: FP64 norms against
+    the oracle's (oracle/diag.py with the same field) within 1e-10."""
+    ny, nx, steps = 70, 150, 40
+    p = dict(tau=0.8, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5, ay=-2e-5)
+    h0, th = random_case(ny, nx, 54)
+    gam = gamma_field(ny, nx, 55)
+    P = lbm.Params(**p)
+    kap = lbm.kappa(th, P)
+    f = lbm.run(lbm.init(h0, P), kap, P, steps, gam)
+    ref = diag.term_norms(f, kap, P, gam)
+    _, _, _, _, sim = gpu_gamma_run(p, h0, th, gam, steps, "fp64")
+    got = sim.term_norms()
+    top = max(ref.values())
+    for k, v in ref.items():
+        assert abs(got[k] - v) <= 1e-10 * v + 1e-14 * top, (k, got[k], v)
+
+
+def test_gamma_field_checks():
+    """A negative or non-finite surface tension sets the status word at init;
+    a field needs a handle created with gamma_field; the reverse pass refuses
+    a handle with the field."""
+    from paper_1810_07642_amd import Sim, TFLBMError
+    from paper_1810_07642_amd._lib import TFLBM_EINVAL, TFLBM_ENONFINITE
+    h0 = torch.full((16, 70), 0.3, dtype=torch.float64)
+    for bad in (-0.01, float("nan"), float("inf")):
+        gam = torch.full_like(h0, 0.01)
+        gam[3, 40] = bad
+        sim = Sim(70, 16, "fp32", hstar=0.1, gamma_field=True).init(h0, None, gam)
+        assert sim.status() == TFLBM_ENONFINITE
+    sim = Sim(70, 16, "fp64", hstar=0.1)
+    with pytest.raises(TFLBMError):
+        sim.init(h0, None, torch.full_like(h0, 0.01))
+    sim = Sim(70, 16, "fp64", hstar=0.1, gamma_field=True).init(h0, None, torch.full_like(h0, 0.01))
+    sim.step(3)
+    adj = torch.empty(sim.adj_bytes(), dtype=torch.uint8, device="cuda")
+    grad_h = torch.zeros_like(h0).cuda()
+    rc = sim.lib.tflbm_adj_seed(sim.h, ctypes.c_void_p(adj.data_ptr()), ctypes.c_void_p(grad_h.data_ptr()),
+                                sim.stream)
+    assert rc == TFLBM_EINVAL
+    torch.cuda.synchronize()

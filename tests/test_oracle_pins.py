@@ -321,3 +321,80 @@ def test_checkerboard_mode_unstable_for_negative_gravity():
     got = np.array([float(((f[l] - base[l]) * cb).mean()) for l in range(9)])
     assert np.abs(got - pred).max() <= 1e-5 * np.abs(pred).max()
     assert abs(got.sum()) > 1.5 * abs(amp0.sum())  # the h mode has grown
+
+
+# ---- position-dependent surface tension (Sec. II, after eq. "n_laplace") -------
+
+def _gamma_case(nx=48, ny=6):
+    x = torch.arange(nx, dtype=torch.float64).view(1, -1).expand(ny, nx)
+    return x
+
+
+def test_uniform_gamma_field_equals_scalar_gamma():
+    """A surface tension field equal to gamma everywhere is the scalar path,
+    bit for bit, for a random state with a kappa field."""
+    g = torch.Generator().manual_seed(71)
+    ny, nx = 9, 13
+    p = lbm.Params(tau=0.9, gamma=0.013, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5)
+    h0 = 0.3 + 0.3 * torch.rand((ny, nx), generator=g, dtype=torch.float64)
+    th = 0.2 + 0.5 * torch.rand((ny, nx), generator=g, dtype=torch.float64)
+    f = lbm.run(lbm.init(h0, p), lbm.kappa(th, p), p, 3)
+    a = lbm.step(f, lbm.kappa(th, p), p)
+    b = lbm.step(f, lbm.kappa(th, p), p, torch.full((ny, nx), 0.013, dtype=torch.float64))
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("mode", [1, 5])
+def test_gamma_field_on_flat_film_gives_closed_form_force(mode):
+    """Flat film h0 at rest with uniform kappa under gamma(x) = gamma0 (1 +
+    eps cos(q x)): the Laplacian vanishes, p = -gamma(x) kappa f(h0), and the
+    isotropic gradient stencil maps cos(q x) to -sin(q) sin(q x) (its symbol
+    for a field varying along x only), so F_x = -h0 gamma0 kappa f(h0) eps
+    sin(q) sin(q x) and F_y = 0.  A reading where gamma(x) multiplies the
+    Laplacian only would give no force here."""
+    nx, ny = 48, 6
+    p = lbm.Params(tau=1.0, gamma=0.0, hstar=0.1, delta=1.0)
+    h0, g0, eps = 0.3, 0.02, 0.25
+    q = 2.0 * math.pi * mode / nx
+    x = _gamma_case(nx, ny)
+    gam = g0 * (1.0 + eps * torch.cos(q * x))
+    kap = lbm.kappa(torch.full((ny, nx), 0.6, dtype=torch.float64), p)
+    h = torch.full((ny, nx), h0, dtype=torch.float64)
+    z = torch.zeros_like(h)
+    fx, fy = lbm.total_force(h, z, z, kap, p, gam)
+    r = p.hstar / h0
+    f0 = r ** 9 - r ** 3
+    want = -h0 * g0 * float(kap[0, 0]) * f0 * eps * math.sin(q) * torch.sin(q * x)
+    assert float((fx - want).abs().max()) <= 1e-13 * float(want.abs().max())
+    assert float(fy.abs().max()) <= 1e-18
+
+
+@pytest.mark.parametrize("k_mode,q_mode", [(1, 3), (4, 1)])
+def test_gamma_field_capillary_pressure_product(k_mode, q_mode):
+    """No disjoining term (theta = 0), h = h0 + a sin(k x), gamma(x) = gamma0
+    (1 + eps cos(q x)).  The Laplacian stencil maps sin(k x) to 2 (cos k - 1)
+    sin(k x) (its symbol along x), so p = -gamma0 L a [sin(k x) + eps/2
+    (sin((k+q) x) + sin((k-q) x))], L = 2 (cos k - 1); the gradient stencil
+    maps sin(K x) to sin(K) cos(K x), which gives F_x = -h(x) d_x p in closed
+    form."""
+    nx, ny = 60, 5
+    p = lbm.Params(tau=1.0, gamma=0.0, hstar=0.1, delta=1.0)
+    h0, a, g0, eps = 0.5, 0.01, 0.01, 0.3
+    k = 2.0 * math.pi * k_mode / nx
+    q = 2.0 * math.pi * q_mode / nx
+    x = _gamma_case(nx, ny)
+    h = h0 + a * torch.sin(k * x)
+    gam = g0 * (1.0 + eps * torch.cos(q * x))
+    z = torch.zeros_like(h)
+    fx, fy = lbm.total_force(h, z, z, torch.zeros_like(h), p, gam)
+    L = 2.0 * (math.cos(k) - 1.0)
+    dpx = -g0 * L * a * (math.sin(k) * torch.cos(k * x)
+                         + 0.5 * eps * (math.sin(k + q) * torch.cos((k + q) * x)
+                                        + math.sin(k - q) * torch.cos((k - q) * x)))
+    want = -h * dpx
+    # the Laplacian cancels terms of size h0 to leave L a: rounding of order
+    # 2^-52 h0 / |L a| relative (1e-11 here); a dropped or misplaced gamma(x)
+    # factor changes F_x by a fraction eps of itself
+    tol = 100 * 2.0 ** -52 * h0 / abs(L * a)
+    assert float((fx - want).abs().max()) <= tol * float(want.abs().max())
+    assert float(fy.abs().max()) <= 1e-18
