@@ -223,7 +223,7 @@ int tflbm_mass_noalloc(const tflbm_sim *sim, double *d_mass, tflbm_stream_t stre
 /* (blocking) TFLBM_OK, or TFLBM_ENONFINITE if a step since tflbm_init met
  * h <= 0 or a non-finite h at an updated site (the height moment of Sec. II,
  * h = sum_l f_l, which divides the momentum in u = j/h and must stay positive
- * for the film pressure's (h_*/h)^n), or if h0 (or a surface tension field)
+ * for the film pressure's (h_* / h)^n), or if h0 (or a surface tension field)
  * had an invalid value.  TFLBM_ESTATE before tflbm_init. */
 int tflbm_check(const tflbm_sim *sim, tflbm_stream_t stream);
 
