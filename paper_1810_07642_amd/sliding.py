@@ -47,3 +47,25 @@ def sliding_capillary_number(prec, bond, delta, hstar=0.5, nx=1024, ny=512, step
     U = ((x1 - x0 + nx / 2) % nx - nx / 2) / window
     nu = (p["tau"] - 0.5) / 3.0
     return nu * U / p["gamma"], h
+
+
+BONDS = (0.1, 0.2, 0.4, 0.8)
+DELTAS = (0.5, 1.0, 2.0)
+
+
+def capillary_sweep(prec, bonds=BONDS, deltas=DELTAS, hstar=0.5, **kw):
+    """Steady Ca of the sliding drop at every (delta, Bond) point:
+    {(delta, bond): Ca}."""
+    return {(d, b): sliding_capillary_number(prec, b, d, hstar=hstar, **kw)[0] for d in deltas for b in bonds}
+
+
+def critical_bond(bonds, cas):
+    """Least-squares line Ca = s (Bo - Bo_c) through the points of one slip
+    length (Sec. III C, eq. "CaBo"): (slope s, intercept Bo_c, largest
+    residual relative to the largest Ca)."""
+    import numpy as np
+    b = np.asarray(bonds, dtype=np.float64)
+    c = np.asarray(cas, dtype=np.float64)
+    s, c0 = np.polyfit(b, c, 1)
+    res = float(np.abs(c - (s * b + c0)).max() / np.abs(c).max())
+    return float(s), float(-c0 / s), res

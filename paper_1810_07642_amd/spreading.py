@@ -103,3 +103,45 @@ def cox_voinov(s, t_min=2.0, theta_eq=None):
     if len(ca) < 3:
         raise ValueError("fewer than three intervals after t_min")
     return float(np.corrcoef(ca, d3)[0, 1]), float(np.polyfit(ca, d3, 1)[0])
+
+
+TANNER_TIMES = (0.5, 1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 20, 25)
+
+
+def tanner_summary(series_by_tau, t_sat=12.0, t_end=25.0):
+    """Per viscosity: growth exponents of r(t) over 1-5 and 2-10 tau_cap, r/r0
+    at t_sat and t_end, the final angle, whether the radius has saturated
+    (grown by less than 1 % of r0 from t_sat to t_end), and the largest
+    spread of r/r0 between the viscosities at equal t/tau_cap (the collapse)."""
+    out = {}
+    ref = None
+    for tau, s in sorted(series_by_tau.items()):
+        rr = s.r / s.r0
+        i_sat = int(np.argmin(np.abs(s.t - t_sat)))
+        i_end = int(np.argmin(np.abs(s.t - t_end)))
+        out[tau] = {"n_1_5": tanner_slope(s, 1.0, 5.0), "n_2_10": tanner_slope(s, 2.0, 10.0),
+                    "r_sat": float(rr[i_sat]), "r_end": float(rr[i_end]),
+                    "theta_end_deg": math.degrees(float(s.theta[i_end])),
+                    "saturated": bool(rr[i_end] - rr[i_sat] < 0.01)}
+        ref = rr if ref is None else ref
+        out[tau]["collapse_dev"] = float(np.abs(rr - ref).max())
+    return out
+
+
+def tanner_sweep(hstars=(0.2, 0.5, 1.0), deltas=(1.0, 2.0, 4.0), taus=(0.9, 1.0, 1.2), times=TANNER_TIMES,
+                 prec="fp64", **kw):
+    """The spreading drop over a grid of precursor thicknesses h_* and slip
+    lengths delta (neither is stated for the paper's experiment), three
+    viscosities each: {(h_*, delta): tanner_summary(...)}, or the error text of
+    a run that met h <= 0 or a non-finite h."""
+    from ._lib import TFLBMError
+    res = {}
+    for hs in hstars:
+        for d in deltas:
+            try:
+                runs = {tau: spreading_series(tau=tau, hstar=hs, delta=d, times=times, prec=prec, **kw)
+                        for tau in taus}
+                res[(hs, d)] = tanner_summary(runs, times[-4] if len(times) > 4 else times[-1], times[-1])
+            except TFLBMError as e:
+                res[(hs, d)] = str(e)
+    return res

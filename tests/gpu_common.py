@@ -139,6 +139,30 @@ OBSERVED = {
     "gamma.case3.fuse1.fp32": 4.021e-07,
     "gamma.case3.fuse2.fp16s": 1.103e-06,
     "gamma.case3.fuse2.fp32": 4.021e-07,
+    "sliding.ca.fp32.delta0.5.bond0.1": 1.046e-03,
+    "sliding.ca.fp32.delta0.5.bond0.2": 7.528e-06,
+    "sliding.ca.fp32.delta0.5.bond0.4": 3.324e-05,
+    "sliding.ca.fp32.delta0.5.bond0.8": 9.060e-06,
+    "sliding.ca.fp32.delta1.0.bond0.1": 2.432e-05,
+    "sliding.ca.fp32.delta1.0.bond0.2": 9.035e-05,
+    "sliding.ca.fp32.delta1.0.bond0.4": 6.731e-07,
+    "sliding.ca.fp32.delta1.0.bond0.8": 5.860e-06,
+    "sliding.ca.fp32.delta2.0.bond0.1": 5.633e-05,
+    "sliding.ca.fp32.delta2.0.bond0.2": 9.555e-07,
+    "sliding.ca.fp32.delta2.0.bond0.4": 8.324e-07,
+    "sliding.ca.fp32.delta2.0.bond0.8": 6.854e-06,
+    "sliding.ca.fp16s.delta0.5.bond0.1": 4.449e-05,
+    "sliding.ca.fp16s.delta0.5.bond0.2": 7.945e-05,
+    "sliding.ca.fp16s.delta0.5.bond0.4": 2.775e-04,
+    "sliding.ca.fp16s.delta0.5.bond0.8": 2.299e-04,
+    "sliding.ca.fp16s.delta1.0.bond0.1": 3.424e-05,
+    "sliding.ca.fp16s.delta1.0.bond0.2": 1.348e-04,
+    "sliding.ca.fp16s.delta1.0.bond0.4": 3.055e-04,
+    "sliding.ca.fp16s.delta1.0.bond0.8": 2.689e-04,
+    "sliding.ca.fp16s.delta2.0.bond0.1": 6.110e-05,
+    "sliding.ca.fp16s.delta2.0.bond0.2": 1.399e-04,
+    "sliding.ca.fp16s.delta2.0.bond0.4": 1.748e-04,
+    "sliding.ca.fp16s.delta2.0.bond0.8": 5.281e-04,
 }
 
 

@@ -1,15 +1,25 @@
 """Spreading dynamics (Sec. III B) on the paper's geometry: 512^2, cap of base
 radius 100 released at theta = pi/6 on a substrate of theta_eq = pi/12, three
-viscosities (tau = 0.9, 1.0, 1.2; tau_cap = 1333, 1667, 2333 steps), h_* = 0.5
-and slip length delta = 4 (the paper states neither), FP64, 25 tau_cap.
+viscosities (tau = 0.9, 1.0, 1.2; tau_cap = 1333, 1667, 2333 steps), FP64,
+50 tau_cap.  The paper states neither the precursor h_* nor the slip length
+delta; h_* = 0.5 here.  In a sweep over h_* in {0.2, 0.5, 1} and delta in
+{1, 2, 4, 8, 16} the growth exponent over 2-10 tau_cap rises with delta
+(0.04-0.08 for delta <= 4, 0.088-0.102 at delta = 8, 0.12-0.14 at delta = 16)
+and so does the speed of the approach to equilibrium.
 
-Checks the paper's statements that hold here, with margins around the measured
-values: the radius curves of the three viscosities collapse when time is
-measured in tau_cap (measured spread 0.6 %); theta^3 - theta_eq^3 is linear in
-the capillary number (Cox-Voinov; measured correlation 0.995); the drop spreads
-monotonically toward theta_eq after the first 2 tau_cap.  The growth exponent
-is measured, 0.07 over 2-10 tau_cap, against Tanner's 1/10, and asserted to lie
-in [0.05, 0.11].
+Checked against the paper's statements, at both slip lengths: the radius
+curves of the three viscosities collapse in t/tau_cap (within 2 % of r0);
+theta^3 - theta_eq^3 is linear in the capillary number (Cox-Voinov); the drop
+relaxes to the cap of its volume with the lubrication equilibrium angle
+arctan(2 sin(theta_eq/2)) = 14.63 deg (the paper's eq. "spherical_cap_vol":
+r/r0 = 1.281 for this volume; within 1 % at 50 tau_cap, the angle within
+0.5 deg).  At delta = 8 the growth exponent over 2-10 tau_cap is Tanner's
+1/10 within 0.015; at delta = 16 the radius saturates (grows by less than
+1 % of r0 from 25 to 50 tau_cap).  No single slip length gives both the
+paper's exponent and its saturation after about 12 tau_cap, and the paper's
+plateau at r/r0 = 1.17 is not reproduced: with this volume it would be a drop
+at about 19.5 deg, 5 deg above the equilibrium angle this disjoining
+pressure sets.
 """
 import math
 
@@ -20,26 +30,46 @@ from gpu_common import banner
 
 pytestmark = pytest.mark.gpu
 
-TIMES = (0.5, 1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 20, 25)
+TIMES = (0.5, 1, 2, 3, 4, 5, 6, 8, 10, 12, 15, 20, 25, 30, 40, 50)
+THETA0, THETA_EQ = math.pi / 6, math.pi / 12
 
 
-def test_spreading_drop_collapse_cox_voinov_tanner():
+def cap_radius_for_volume(vol, theta):
+    """Base radius of the spherical cap of volume vol and contact angle theta
+    (Sec. III B, eq. "spherical_cap_vol", R the sphere radius)."""
+    R = (vol / (math.pi / 3.0 * (2.0 + math.cos(theta)) * (1.0 - math.cos(theta)) ** 2)) ** (1.0 / 3.0)
+    return R * math.sin(theta)
+
+
+@pytest.mark.parametrize("delta", [8.0, 16.0])
+def test_spreading_drop_collapse_cox_voinov_tanner(delta):
+    from paper_1810_07642_amd import inputs
     from paper_1810_07642_amd.spreading import cox_voinov, spreading_series, tanner_slope
-    banner("spreading drop 512^2, three viscosities, 25 tau_cap")
-    runs = {tau: spreading_series(tau=tau, times=TIMES) for tau in (0.9, 1.0, 1.2)}
+    banner(f"spreading drop 512^2, delta {delta}, three viscosities, 50 tau_cap")
+    hstar = 0.5
+    runs = {tau: spreading_series(tau=tau, hstar=hstar, delta=delta, times=TIMES) for tau in (0.9, 1.0, 1.2)}
+    apex = inputs.apex_from_angle(100.0, THETA0)
+    vol = float((inputs.spherical_cap(512, 512, 100.0, apex, hstar) - hstar).sum())
+    th_lub = math.atan(2.0 * math.sin(THETA_EQ / 2.0))
     ref = runs[1.0]
+    i25, i50 = TIMES.index(25) + 1, TIMES.index(50) + 1
     for tau, s in runs.items():
         rr = s.r / s.r0
+        r_eq = cap_radius_for_volume(vol, th_lub) / s.r0
         dev = float(np.abs(rr - ref.r / ref.r0).max())
         corr, slope = cox_voinov(s, t_min=2.0)
         n = tanner_slope(s, 2.0, 10.0)
-        print(f"tau {tau}: tau_cap {s.tau_cap:.0f}, r/r0 at 12 tau_cap {rr[TIMES.index(12) + 1]:.3f}, "
-              f"at 25 {rr[-1]:.3f}, theta {math.degrees(s.theta[-1]):.1f} deg, collapse dev {dev:.4f}, "
-              f"Cox-Voinov corr {corr:.4f} slope {slope:.2f}, growth exponent {n:.3f}")
-        assert dev < 0.015
+        print(f"delta {delta} tau {tau}: tau_cap {s.tau_cap:.0f}, growth exponent (2-10) {n:.3f}, r/r0 at 25 "
+              f"{rr[i25]:.4f}, at 50 {rr[i50]:.4f} (volume-conserving cap at {math.degrees(th_lub):.2f} deg: "
+              f"{r_eq:.4f}), theta {math.degrees(s.theta[-1]):.2f} deg, collapse dev {dev:.4f}, "
+              f"Cox-Voinov corr {corr:.4f}", flush=True)
+        assert dev < 0.02
         assert corr > 0.98 and slope > 0
-        assert 0.05 <= n <= 0.11
         late = s.t >= 2.0
         assert np.all(np.diff(s.r[late]) > 0) and np.all(np.diff(s.theta[late]) < 0)
-        assert rr[-1] > 1.15
-        assert math.pi / 12 < s.theta[-1] < math.pi / 12 + math.radians(4)
+        assert abs(rr[i50] - r_eq) <= 0.01 * r_eq
+        assert abs(s.theta[-1] - th_lub) <= math.radians(0.5)
+        if delta == 8.0:
+            assert abs(n - 0.1) <= 0.015
+        else:
+            assert rr[i50] - rr[i25] < 0.01
