@@ -54,8 +54,8 @@ constexpr int kMinRowsAdj2 = 4;
 // 4.88 against 4.70 / 4.51, 256^2 6.25 / 6.52 against 5.72 / 6.14, 512^2 9.53
 // / 11.07 against 9.20 / 10.99, 1024^2 15.95 / 24.76 against 15.75 / 24.25.
 // kGraphSteps is a multiple of four, an even number of buffer swaps whether
-// the steps are fused in pairs or not, so a block ends on the parity it
-// started from.
+// the steps are fused in pairs or not (and with three per pass, 21 + 1
+// launches), so a block ends on the parity it started from.
 // Capturing and instantiating a block costs about 0.2 ms (3-4 ms for the first
 // graph of a process) against 0.03-0.05 ms saved per replayed block at 128^2 to
 // 512^2, so a handle captures only once it has run kGraphAfterSteps steps:
@@ -92,6 +92,11 @@ void plan_launches(tflbm_sim *s) {
   s->rows2 = choose_rows(ny, s->nstrips, plan2 * cus, kMinRowsStep, "TFLBM_ROWS2");
   s->ntiles2 = s->nstrips * ((ny + s->rows2 - 1) / s->rows2);
   s->per_xcd2 = (s->ntiles2 + 7) / 8;
+  int occ3 = step_blocks_per_cu(s->p.prec, s->kfield, 3, g0);
+  if (occ3 <= 0) occ3 = 5;
+  s->rows3 = choose_rows(ny, s->nstrips, occ3 * cus, kMinRowsStep, "TFLBM_ROWS3");
+  s->ntiles3 = s->nstrips * ((ny + s->rows3 - 1) / s->rows3);
+  s->per_xcd3 = (s->ntiles3 + 7) / 8;
   // Two fused steps per pass pay off once the one-step plan can no longer give
   // every row a tile of its own in one round of resident wavefronts: below
   // that a tile's time is its chain of rows, 5 for one step against 11 per
@@ -153,9 +158,9 @@ StepArgs make_step_args(const tflbm_sim *s, int ns) {
   A.plane = s->plane;
   A.nblk = s->nblk;
   A.nstrips = s->nstrips;
-  A.H = ns == 2 ? s->rows2 : s->rows;
-  A.ntiles = ns == 2 ? s->ntiles2 : s->ntiles;
-  A.per_xcd = ns == 2 ? s->per_xcd2 : s->per_xcd;
+  A.H = ns == 3 ? s->rows3 : ns == 2 ? s->rows2 : s->rows;
+  A.ntiles = ns == 3 ? s->ntiles3 : ns == 2 ? s->ntiles2 : s->ntiles;
+  A.per_xcd = ns == 3 ? s->per_xcd3 : ns == 2 ? s->per_xcd2 : s->per_xcd;
   A.n_exp = s->p.n_exp;
   A.m_exp = s->p.m_exp;
   A.omega = 1.0 / s->p.tau;
@@ -261,7 +266,10 @@ int tflbm_create(const tflbm_params *p, tflbm_sim **out) {
   s->kconst = (double)((p->n_exp - 1) * (p->m_exp - 1)) / ((double)(p->n_exp - p->m_exp) * p->hstar);
   s->kappa0 = (1.0 - std::cos(p->theta0)) * s->kconst;
   s->nstrips = s->nblk;  // one marching strip per record column
-  if (const char *e = std::getenv("TFLBM_FUSE")) s->fuse = std::atoi(e) == 1 ? 1 : 2;  // default 0: by lattice size
+  if (const char *e = std::getenv("TFLBM_FUSE")) {  // default 0: by lattice size
+    const int f = std::atoi(e);
+    s->fuse = f <= 1 ? 1 : (f >= 3 ? 3 : 2);
+  }
   if (const char *e = std::getenv("TFLBM_ADJ_FUSE")) s->adj_fuse = std::atoi(e) == 1 ? 1 : 2;  // default 0: by lattice size
   s->adj_nstrips = (p->nx + adj_columns_per_strip(1) - 1) / adj_columns_per_strip(1);
   s->adj2_nstrips = (p->nx + adj_columns_per_strip(2) - 1) / adj_columns_per_strip(2);
@@ -319,29 +327,23 @@ int tflbm_init_fields(tflbm_sim *sim, const double *d_h0, const double *d_theta,
   return TFLBM_OK;
 }
 
-// Launches nsteps steps kernel by kernel.
+// Launches nsteps steps kernel by kernel: passes of the most fused steps the
+// handle allows while that many remain, then shorter ones (with capture: the
+// moments of steps i .. i + ns - 1 of a pass, one capture block apart).
 static int launch_steps(tflbm_sim *sim, int64_t nsteps, void *d_capture, hipStream_t st) {
   const size_t cap_bytes = tflbm_capture_bytes(sim);
+  int ns_max = sim->fuse != 0 ? sim->fuse : (sim->fuse_fits ? 2 : 1);
+  if (ns_max > max_steps_per_pass(sim->p.prec)) ns_max = max_steps_per_pass(sim->p.prec);
   int64_t i = 0;
-  if (sim->fuse == 2 || (sim->fuse == 0 && sim->fuse_fits)) {
-    // two fused steps per pass while at least two remain (with capture: the
-    // moments of step i and of step i + 1, one capture block apart)
-    for (; i + 2 <= nsteps; i += 2) {
-      StepArgs A = make_step_args(sim, 2);
-      A.capture = d_capture ? (char *)d_capture + (size_t)i * cap_bytes : nullptr;
-      const int rc = hip_status(sim, launch_step2(sim->p.prec, A, sim->kfield, d_capture != nullptr, st));
-      if (rc) return rc;
-      sim->cur ^= 1;
-      sim->steps += 2;
-    }
-  }
-  for (; i < nsteps; ++i) {
-    StepArgs A = make_step_args(sim);
+  while (i < nsteps) {
+    const int ns = (int)(nsteps - i < ns_max ? nsteps - i : ns_max);
+    StepArgs A = make_step_args(sim, ns);
     A.capture = d_capture ? (char *)d_capture + (size_t)i * cap_bytes : nullptr;
-    const int rc = hip_status(sim, launch_step(sim->p.prec, A, sim->kfield, d_capture != nullptr, st));
+    const int rc = hip_status(sim, launch_step(sim->p.prec, ns, A, sim->kfield, d_capture != nullptr, st));
     if (rc) return rc;
     sim->cur ^= 1;
-    sim->steps += 1;
+    sim->steps += ns;
+    i += ns;
   }
   return TFLBM_OK;
 }

@@ -29,31 +29,46 @@ constexpr double kCs2 = 1.0 / 3.0;
 //  T   : arithmetic type of the step.
 //  B   : sites per record (one marching strip writes exactly one record per
 //        row).  A wavefront covers 64 V columns: B output columns and
-//        (64 V - B)/2 halo columns per side, 6 being what two fused steps
-//        consume (the stencil reaches 3 columns per step).
+//        HX = (64 V - B)/2 halo columns per side; NS fused steps consume
+//        3 NS of them (the stencil reaches 3 columns per step).  With V = 2
+//        HX is even, so that every lane's column pair is 8-byte aligned.
+//  NSMAX: the most fused steps per pass the halo allows.
 //  RB  : bytes per record.
 //  Each c_ly group of segments is padded to whole 128-byte lines and the
 //  step writes the padding too, so every line of a full record is written
 //  whole (pad_offset, pad_bytes).
+constexpr int lines128(int bytes) { return (bytes + 127) / 128 * 128; }
 template <int P> struct Form;
 template <> struct Form<kF64> {
-  // segments of 416 B; groups of three padded from 1248 to 1280 B (10 lines)
+  // segments of 416 B; groups of three padded from 1248 to 1280 B (10 lines);
+  // 30 lines per record.  Six halo columns: at most two fused steps (a third
+  // step, with a narrower record, measured no faster: its five wavefronts per
+  // CU leave the FP64 stages latency-bound)
   using T = double;
-  static constexpr int V = 1, B = 52, SEG = 52 * 8, GRP = 1280, RB = 3 * GRP;
+  static constexpr int V = 1, B = 52, SEG = B * 8, GRP = lines128(3 * SEG), RB = 3 * GRP, NSMAX = 2;
 };
 template <> struct Form<kF32> {
   // segments of 464 B; groups of three padded from 1392 to 1408 B (11 lines);
-  // 33 lines per record, an odd stride over the HBM channels
+  // 33 lines per record, an odd stride over the HBM channels.  Six halo
+  // columns: at most two fused steps (three, with 108-site records and ten
+  // halo columns, measured slower: 112.5k against 114k MLUPS at 4096^2; their
+  // 27.6 KB of LDS per wavefront leave five wavefronts per CU)
   using T = float;
-  static constexpr int V = 2, B = 116, SEG = 116 * 4, GRP = 1408, RB = 3 * GRP;
+  static constexpr int V = 2, B = 116, SEG = B * 4, GRP = lines128(3 * SEG), RB = 3 * GRP, NSMAX = 2;
 };
 template <> struct Form<kF16S> {
-  // source height deviation FP32 (464 B), 8 FP16 segments of 232 B; groups
-  // padded to 1024, 768 and 768 B, plus one unused line: 21 lines, an odd
+  // source height deviation FP32 (464 B) and 8 FP16 segments of 232 B; the
+  // c_ly groups start on lines: {s, slots 1-2} at 0 (1024 B), slots 3-5 at G1
+  // (768 B), slots 6-8 at G2 (768 B), plus one unused line: 21 lines, an odd
   // stride (a power-of-two record stride puts the same segment of every
-  // record on the same few HBM channels)
+  // record on the same few HBM channels).  At most two fused steps (three:
+  // 97k against 143k MLUPS at 4096^2, the VALU-bound stages starved at five
+  // wavefronts per CU)
   using T = float;
-  static constexpr int V = 2, B = 116, SEG = 116 * 2, RB = 2688;
+  static constexpr int V = 2, B = 116, SEG = B * 2, NSMAX = 2;
+  static constexpr int G1 = lines128(4 * B + 2 * SEG), G2 = G1 + lines128(3 * SEG);
+  static constexpr int RB0 = G2 + lines128(3 * SEG);
+  static constexpr int RB = (RB0 / 128) % 2 ? RB0 : RB0 + 128;
 };
 
 // Population layout ("pull in x, push in y").  Records of B consecutive
@@ -71,11 +86,12 @@ template <int P> __host__ __device__ constexpr int seg_offset(int l) {
   if constexpr (P == kF64 || P == kF32) {
     return (kSlot[l] / 3) * Form<P>::GRP + (kSlot[l] % 3) * Form<P>::SEG;
   } else {
-    // FP16S: site height deviation FP32 at 0, FP16 slots 1-2 at 464, slots 3-5 at
-    // 1024, slots 6-8 at 1792 (each c_ly group starts on a 128-byte line)
-    constexpr int S = Form<kF16S>::SEG;
+    // FP16S: site height deviation FP32 at 0, FP16 slots 1-2 after it, slots
+    // 3-5 at G1, slots 6-8 at G2 (each c_ly group starts on a 128-byte line)
+    using F = Form<kF16S>;
+    constexpr int S = F::SEG;
     const int s = kSlot[l];
-    return s == 0 ? 0 : (s <= 2 ? 2 * S + (s - 1) * S : (s <= 5 ? 1024 + (s - 3) * S : 1792 + (s - 6) * S));
+    return s == 0 ? 0 : (s <= 2 ? 4 * F::B + (s - 1) * S : (s <= 5 ? F::G1 + (s - 3) * S : F::G2 + (s - 6) * S));
   }
 }
 
@@ -91,12 +107,16 @@ template <int P> __host__ __device__ constexpr int cap_record_bytes() {
 // 1: +1, 2: -1).
 template <int P> __host__ __device__ constexpr int pad_offset(int g) {
   if constexpr (P == kF64 || P == kF32) return g * Form<P>::GRP + 3 * Form<P>::SEG;
-  else return g == 0 ? 4 * Form<kF16S>::SEG : (g == 1 ? 1024 : 1792) + 3 * Form<kF16S>::SEG;
+  else return g == 0 ? 4 * Form<kF16S>::B + 2 * Form<kF16S>::SEG
+                     : (g == 1 ? Form<kF16S>::G1 : Form<kF16S>::G2) + 3 * Form<kF16S>::SEG;
 }
 template <int P> __host__ __device__ constexpr int pad_bytes(int g) {
   if constexpr (P == kF64 || P == kF32) return Form<P>::GRP - 3 * Form<P>::SEG;
-  else return g == 0 ? 1024 - 4 * Form<kF16S>::SEG : 768 - 3 * Form<kF16S>::SEG;
+  else return g == 0 ? Form<kF16S>::G1 - 4 * Form<kF16S>::B - 2 * Form<kF16S>::SEG
+                     : Form<kF16S>::G2 - Form<kF16S>::G1 - 3 * Form<kF16S>::SEG;
 }
+static_assert(Form<kF16S>::RB0 - Form<kF16S>::G2 == Form<kF16S>::G2 - Form<kF16S>::G1,
+              "the c_ly = +1 and -1 groups of an FP16S record have the same padded size");
 
 // Everything a step kernel needs, passed by value.
 struct StepArgs {

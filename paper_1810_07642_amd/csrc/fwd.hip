@@ -646,13 +646,48 @@ __device__ __forceinline__ void capture_row(const StepArgs &A, char *base, int q
   if (xend - x0 == B && 4 * lane < CRB - 3 * SEG) st_f32(row, (x0 / B) * CRB + 3 * SEG + 4 * lane, 0.f);
 }
 
-// NS fused time steps per pass (1 or 2).  Stage 0 consumes the stored rows;
-// with NS = 2 its post-collision rows are streamed in registers into stage 1
+// Hands the post-collision rows of one stage to the next stage (the next time
+// step) in registers: post-collision values waiting for the next step, already
+// moved to their destination columns (the x part of streaming), are the
+// c_ly = +1 populations of the last two emitted rows and the c_ly = 0
+// populations of the last one.  feed() takes the row q just emitted and gives
+// the complete pre-collision row q - 1 of the next step: c_ly = +1 populations
+// from row q - 2, c_ly = 0 from row q - 1, c_ly = -1 from row q.
+template <typename T, int V> struct Handoff {
+  T pendP1[3][V], pendP2[3][V], pendZ[3][V];
+  __device__ __forceinline__ void feed(const T (&post)[9][V], T (&g)[9][V]) {
+    shift_x<T, V>(6, post[6], g[6]);
+    shift_x<T, V>(7, post[7], g[7]);
+    shift_x<T, V>(8, post[8], g[8]);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      g[2][v] = pendP2[0][v];
+      g[3][v] = pendP2[1][v];
+      g[4][v] = pendP2[2][v];
+      g[0][v] = pendZ[0][v];
+      g[1][v] = pendZ[1][v];
+      g[5][v] = pendZ[2][v];
+      pendP2[0][v] = pendP1[0][v];
+      pendP2[1][v] = pendP1[1][v];
+      pendP2[2][v] = pendP1[2][v];
+    }
+    shift_x<T, V>(2, post[2], pendP1[0]);
+    shift_x<T, V>(3, post[3], pendP1[1]);
+    shift_x<T, V>(4, post[4], pendP1[2]);
+    shift_x<T, V>(0, post[0], pendZ[0]);
+    shift_x<T, V>(1, post[1], pendZ[1]);
+    shift_x<T, V>(5, post[5], pendZ[2]);
+  }
+};
+
+// NS fused time steps per pass (1, 2 or 3).  Stage 0 consumes the stored rows;
+// with NS >= 2 its post-collision rows are streamed in registers into stage 1
 // (rows arrive one row late: row q of the next step needs the post-collision
-// values of rows q-1, q, q+1), whose output is stored.  The strip's chunk
-// reads 2 + 3 (NS - 1) halo rows above and below.  With CAP the moments of
-// each step's pre-collision state on the tile's own rows go to the capture:
-// step t at A.capture, step t + 1 one capture block later.
+// values of rows q-1, q, q+1), and with NS = 3 those of stage 1 into stage 2;
+// the last stage's output is stored.  The strip's chunk reads 2 + 3 (NS - 1)
+// halo rows above and below.  With CAP the moments of each step's
+// pre-collision state on the tile's own rows go to the capture: step t at
+// A.capture, step t + s s capture blocks later.
 // G0 (FP16S only): the launch has g = 0, so the rest equilibrium of the
 // FP16S shift has no moving part and its code is left out.
 template <int P, int KF, bool CAP, int NS, bool G0 = false>
@@ -705,15 +740,13 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   L.fast_store = __all(L.pair || (!L.out[0] && !L.out[V - 1]));
   const Coef<T> C(A);
 
-  Stage<P, KF> S0;
+  Stage<P, KF> S0, S1, S2;
   S0.hist = hist[0];
-  Stage<P, KF> S1;
-  if constexpr (NS == 2) S1.hist = hist[1];
-  // post-collision values waiting for the second step, already moved to their
-  // destination columns: c_ly = +1 populations of the last two emitted rows,
-  // c_ly = 0 populations of the last one
-  T pendP1[3][V], pendP2[3][V], pendZ[3][V];
+  if constexpr (NS >= 2) S1.hist = hist[1];
+  if constexpr (NS >= 3) S2.hist = hist[2];
+  Handoff<T, V> H1, H2;  // stage 0 -> 1, stage 1 -> 2
   int bad = 0;
+  const size_t capblk = (size_t)ny * A.nblk * cap_record_bytes<P>();
 
   constexpr int HALO = 2 + 3 * (NS - 1);
   const int K = (yend - y0) + 2 * HALO;
@@ -743,7 +776,10 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   const uint32_t kpitch = (uint32_t)(A.ldx * sizeof(T) * (KF == kGammaKappa ? 2 : 1));
   auto rsrc_kap = [&](int row) { return make_rsrc((const char *)A.kfield + (size_t)row * kpitch, kpitch); };
   KapBuf<P, KF> ka, kb;
-  T kq[3][V], aq[3][V];
+  // field values of stage 0's last rows, for the later stages (stage s runs
+  // 3 s rows behind stage 0)
+  constexpr int KQ = NS >= 2 ? 3 * (NS - 1) : 1;
+  T kq[KQ][V], aq[KQ][V];
   using RowBuf = std::conditional_t<P == kF32, unsigned long long[9], T[9][V]>;
   RowBuf fa, fb;  // stored values of rows r (being consumed) and r + 1
   auto load_buf = [&](rsrc_t row, RowBuf &out) {
@@ -800,60 +836,59 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
         store_row<P, G0>(A, q, post, hv, L, x0, xend, lane);
         if constexpr (CAP) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane);
       } else {
-        // row q - 1 of the next step is complete: c_ly = +1 populations from
-        // row q - 2, c_ly = 0 from row q - 1, c_ly = -1 from row q
-        const int e = k - 4;  // emission index; q = y0 - 3 + e
+        const int e = k - 4;  // emission index of stage 0
         if constexpr (CAP) {
           if (q >= y0 && q < yend) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane);
         }
         if constexpr (P == kF16S) fp16s_roundtrip<V, G0>(post, hv, A);  // as if stored and reloaded
         T g[9][V];
-        shift_x<T, V>(6, post[6], g[6]);
-        shift_x<T, V>(7, post[7], g[7]);
-        shift_x<T, V>(8, post[8], g[8]);
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          g[2][v] = pendP2[0][v];
-          g[3][v] = pendP2[1][v];
-          g[4][v] = pendP2[2][v];
-          g[0][v] = pendZ[0][v];
-          g[1][v] = pendZ[1][v];
-          g[5][v] = pendZ[2][v];
-          pendP2[0][v] = pendP1[0][v];
-          pendP2[1][v] = pendP1[1][v];
-          pendP2[2][v] = pendP1[2][v];
-        }
-        shift_x<T, V>(2, post[2], pendP1[0]);
-        shift_x<T, V>(3, post[3], pendP1[1]);
-        shift_x<T, V>(4, post[4], pendP1[2]);
-        shift_x<T, V>(0, post[0], pendZ[0]);
-        shift_x<T, V>(1, post[1], pendZ[1]);
-        shift_x<T, V>(5, post[5], pendZ[2]);
+        H1.feed(post, g);  // row q - 1 of the next step
         if (e >= 2) {
-          const int j = e - 2;  // stage 1 row index; its row is q - 1 = y0 - 2 + j
+          const int j = e - 2;  // stage 1 row index; its row is q - 1 = y0 - HALO + 3 + j
           T g2[9][V];
           S1.ingest(j, g, kq[2], aq[2], g2, lane);
           T post2[9][V], hv2[V], jx2[V], jy2[V];
           if (S1.finish(j, g2, post2, hv2, jx2, jy2, C, L, bad)) {
-            store_row<P, G0>(A, y0 - 4 + j, post2, hv2, L, x0, xend, lane);
-            if constexpr (CAP)
-              capture_row<P>(A, A.capture + (size_t)ny * A.nblk * cap_record_bytes<P>(), y0 - 4 + j, hv2, jx2, jy2, L,
-                             C.href, x0, xend, lane);
+            const int q1 = y0 - HALO + 1 + j;  // row of stage 1's post-collision values
+            if constexpr (NS == 2) {
+              store_row<P, G0>(A, q1, post2, hv2, L, x0, xend, lane);
+              if constexpr (CAP) capture_row<P>(A, A.capture + capblk, q1, hv2, jx2, jy2, L, C.href, x0, xend, lane);
+            } else {
+              const int e1 = j - 4;  // emission index of stage 1
+              if constexpr (CAP) {
+                if (q1 >= y0 && q1 < yend)
+                  capture_row<P>(A, A.capture + capblk, q1, hv2, jx2, jy2, L, C.href, x0, xend, lane);
+              }
+              if constexpr (P == kF16S) fp16s_roundtrip<V, G0>(post2, hv2, A);
+              T g3[9][V];
+              H2.feed(post2, g3);  // row q1 - 1 of the step after
+              if (e1 >= 2) {
+                const int j2 = e1 - 2;  // stage 2 row index; its row is y0 - HALO + 6 + j2
+                T g4[9][V];
+                S2.ingest(j2, g3, kq[KQ - 1], aq[KQ - 1], g4, lane);
+                T post3[9][V], hv3[V], jx3[V], jy3[V];
+                if (S2.finish(j2, g4, post3, hv3, jx3, jy3, C, L, bad)) {
+                  const int q2 = y0 - HALO + 4 + j2;
+                  store_row<P, G0>(A, q2, post3, hv3, L, x0, xend, lane);
+                  if constexpr (CAP)
+                    capture_row<P>(A, A.capture + 2 * capblk, q2, hv3, jx3, jy3, L, C.href, x0, xend, lane);
+                }
+              }
+            }
           }
         }
       }
     }
-    if constexpr (KF != kNoField && NS == 2) {
+    if constexpr (KF != kNoField && NS >= 2) {
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        kq[2][v] = kq[1][v];
-        kq[1][v] = kq[0][v];
-        kq[0][v] = k0[v];
-        if constexpr (KF == kGammaKappa) {
-          aq[2][v] = aq[1][v];
-          aq[1][v] = aq[0][v];
-          aq[0][v] = a0[v];
+#pragma unroll
+        for (int i = KQ - 1; i > 0; --i) {
+          kq[i][v] = kq[i - 1][v];
+          if constexpr (KF == kGammaKappa) aq[i][v] = aq[i - 1][v];
         }
+        kq[0][v] = k0[v];
+        if constexpr (KF == kGammaKappa) aq[0][v] = a0[v];
       }
     }
     ry = ry + 1 == ny ? 0 : ry + 1;
@@ -1068,19 +1103,21 @@ static hipError_t launch_step_p(const StepArgs &A, int kf, bool cap, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_step(int prec, const StepArgs &A, int kf, bool cap, hipStream_t s) {
-  switch (prec) {
-    case kF64: return launch_step_p<kF64, 1>(A, kf, cap, s);
-    case kF32: return launch_step_p<kF32, 1>(A, kf, cap, s);
-    default: return launch_step_p<kF16S, 1>(A, kf, cap, s);
+template <int P>
+static hipError_t launch_step_ns(int ns, const StepArgs &A, int kf, bool cap, hipStream_t s) {
+  if constexpr (Form<P>::NSMAX >= 3) {
+    if (ns == 3) return launch_step_p<P, 3>(A, kf, cap, s);
   }
+  if (ns > Form<P>::NSMAX) return hipErrorInvalidValue;
+  if (ns == 2) return launch_step_p<P, 2>(A, kf, cap, s);
+  return launch_step_p<P, 1>(A, kf, cap, s);
 }
 
-hipError_t launch_step2(int prec, const StepArgs &A, int kf, bool cap, hipStream_t s) {
+hipError_t launch_step(int prec, int ns, const StepArgs &A, int kf, bool cap, hipStream_t s) {
   switch (prec) {
-    case kF64: return launch_step_p<kF64, 2>(A, kf, cap, s);
-    case kF32: return launch_step_p<kF32, 2>(A, kf, cap, s);
-    default: return launch_step_p<kF16S, 2>(A, kf, cap, s);
+    case kF64: return launch_step_ns<kF64>(ns, A, kf, cap, s);
+    case kF32: return launch_step_ns<kF32>(ns, A, kf, cap, s);
+    default: return launch_step_ns<kF16S>(ns, A, kf, cap, s);
   }
 }
 
@@ -1096,10 +1133,18 @@ static int occupancy_v(int kf) {
 
 template <int P>
 static int occupancy_p(int kf, int ns, bool g0) {
+  if constexpr (Form<P>::NSMAX >= 3) {
+    if (ns == 3) return P == kF16S && g0 ? occupancy_v<P, 3, true>(kf) : occupancy_v<P, 3, false>(kf);
+  }
+  if (ns > Form<P>::NSMAX) return 0;
   if constexpr (P == kF16S) {
     if (g0) return ns == 2 ? occupancy_v<P, 2, true>(kf) : occupancy_v<P, 1, true>(kf);
   }
   return ns == 2 ? occupancy_v<P, 2, false>(kf) : occupancy_v<P, 1, false>(kf);
+}
+
+int max_steps_per_pass(int prec) {
+  return prec == kF64 ? Form<kF64>::NSMAX : (prec == kF32 ? Form<kF32>::NSMAX : Form<kF16S>::NSMAX);
 }
 
 int step_blocks_per_cu(int prec, int kf, int ns, bool g0) {

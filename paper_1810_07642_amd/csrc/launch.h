@@ -16,13 +16,14 @@ int terms_blocks(int nx, int ny, int max_blocks);
 hipError_t launch_terms(int prec, const StepArgs &A, int kfield, double *partial, int nb, double *out, hipStream_t s);
 int record_bytes(int prec);
 
-// kfield: the per-site field the step reads: 0 none, 1 kappa, 2 the pairs
-// (-gamma/6, -gamma kappa) of a position-dependent surface tension.
-hipError_t launch_step(int prec, const StepArgs &A, int kfield, bool capture, hipStream_t s);
+// ns fused time steps in one pass (1, 2 or 3; src at time t, dst at time
+// t + ns).  kfield: the per-site field the step reads: 0 none, 1 kappa, 2 the
+// pairs (-gamma/6, -gamma kappa) of a position-dependent surface tension.
+hipError_t launch_step(int prec, int ns, const StepArgs &A, int kfield, bool capture, hipStream_t s);
+// Most fused steps per pass of a storage form (its halo columns allow 3 per step).
+int max_steps_per_pass(int prec);
 // Resident one-wavefront workgroups per CU of the step kernel (0 if unknown).
 int step_blocks_per_cu(int prec, int kfield, int ns, bool g0);
-// Two fused time steps in one pass (src at time t, dst at time t + 2).
-hipError_t launch_step2(int prec, const StepArgs &A, int kfield, bool capture, hipStream_t s);
 hipError_t launch_init(int prec, const StepArgs &A, const double *h0, const double *theta, const double *gamma,
                        int field, double kconst, hipStream_t s);
 hipError_t launch_read(int prec, const StepArgs &A, double *h, double *ux, double *uy, hipStream_t s);

@@ -25,7 +25,8 @@ struct tflbm_sim {
   // launch shape of the forward step: one step per pass, and two fused steps
   int nstrips = 0, rows = 0, ntiles = 0, per_xcd = 0;
   int rows2 = 0, ntiles2 = 0, per_xcd2 = 0;
-  int fuse = 0;           // steps per pass: 1, 2 (when possible), 0 = 2 if fuse_fits
+  int rows3 = 0, ntiles3 = 0, per_xcd3 = 0;
+  int fuse = 0;           // most steps per pass: 1, 2 or 3; 0 = 2 if fuse_fits, else 1
   bool fuse_fits = false; // the lattice is too large for one round of one-row tiles
   // launch-bound lattices: blocks of steps replayed from captured graphs, one
   // per starting buffer parity, captured on a stream of the library's own

@@ -9,12 +9,12 @@ and so does the speed of the approach to equilibrium.
 
 Checked against the paper's statements, at both slip lengths: the radius
 curves of the three viscosities collapse in t/tau_cap (within 2 % of r0);
-theta^3 - theta_eq^3 is linear in the capillary number (Cox-Voinov); the drop
-relaxes to the cap of its volume with the lubrication equilibrium angle
+the drop relaxes to the cap of its volume with the lubrication equilibrium angle
 arctan(2 sin(theta_eq/2)) = 14.63 deg (the paper's eq. "spherical_cap_vol":
 r/r0 = 1.281 for this volume; within 1 % at 50 tau_cap, the angle within
-0.5 deg).  At delta = 8 the growth exponent over 2-10 tau_cap is Tanner's
-1/10 within 0.015; at delta = 16 the radius saturates (grows by less than
+0.5 deg).  At delta = 8, where the drop spreads through the whole run, the
+growth exponent over 2-10 tau_cap is Tanner's 1/10 within 0.015 and theta^3 -
+theta_eq^3 is linear in the capillary number (Cox-Voinov); at delta = 16 the radius saturates (grows by less than
 1 % of r0 from 25 to 50 tau_cap).  No single slip length gives both the
 paper's exponent and its saturation after about 12 tau_cap, and the paper's
 plateau at r/r0 = 1.17 is not reproduced: with this volume it would be a drop
@@ -64,12 +64,15 @@ def test_spreading_drop_collapse_cox_voinov_tanner(delta):
               f"{r_eq:.4f}), theta {math.degrees(s.theta[-1]):.2f} deg, collapse dev {dev:.4f}, "
               f"Cox-Voinov corr {corr:.4f}", flush=True)
         assert dev < 0.02
-        assert corr > 0.98 and slope > 0
         late = s.t >= 2.0
         assert np.all(np.diff(s.r[late]) > 0) and np.all(np.diff(s.theta[late]) < 0)
         assert abs(rr[i50] - r_eq) <= 0.01 * r_eq
         assert abs(s.theta[-1] - th_lub) <= math.radians(0.5)
         if delta == 8.0:
+            # spreading through the whole run: Tanner and Cox-Voinov
             assert abs(n - 0.1) <= 0.015
+            assert corr > 0.98 and slope > 0
         else:
+            # at rest from about 20 tau_cap on: the late line speeds and angle
+            # excesses are rounding, so Cox-Voinov is not asserted here
             assert rr[i50] - rr[i25] < 0.01
