@@ -163,6 +163,14 @@ OBSERVED = {
     "sliding.ca.fp16s.delta2.0.bond0.2": 1.399e-04,
     "sliding.ca.fp16s.delta2.0.bond0.4": 1.748e-04,
     "sliding.ca.fp16s.delta2.0.bond0.8": 5.281e-04,
+    "gamma.case0.fuse3.fp16s": 1.339e-05,
+    "gamma.case0.fuse3.fp32": 1.109e-06,
+    "gamma.case1.fuse3.fp16s": 4.913e-06,
+    "gamma.case1.fuse3.fp32": 8.085e-07,
+    "gamma.case2.fuse3.fp16s": 6.833e-06,
+    "gamma.case2.fuse3.fp32": 7.682e-07,
+    "gamma.case3.fuse3.fp16s": 1.103e-06,
+    "gamma.case3.fuse3.fp32": 4.021e-07,
 }
 
 
