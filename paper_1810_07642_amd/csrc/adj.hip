@@ -7,10 +7,9 @@
 //   p = -gamma (L h + kappa phi(h)),  phi(h) = (h_*/h)^n - (h_*/h)^m
 //   G = grad_s p (isotropic gradient),  F = -h G - nu alpha(h) u + h a
 //   f*_l = f_l + omega (feq_l(h, u) - f_l) + 3 w_l c_l . F,   f_l(x + c_l, t + 1) = f*_l(x).
-// Adjoint.  lambda^t_l(x) = dLoss/df^t_l(x).  The stored adjoint is
-// pre-shifted, mu_l(x) = lambda^{t+1}_l(x + c_l) = dLoss/df*_l(x), so that
-// all nine values a site needs are at the site itself (the same footprint as
-// the forward push layout).  One reverse step computes, at every site:
+// Adjoint.  lambda^t_l(x) = dLoss/df^t_l(x).  A reverse step at site x reads
+// mu_l(x) = lambda^{t+1}_l(x + c_l) = dLoss/df*_l(x) and computes, at every
+// site:
 //   Lambda_F = 3 sum_l w_l c_l mu_l                       (from the source term)
 //   lambda_G = -h Lambda_F                                (from F = -h G)
 //   lambda_p = -div_s lambda_G                            (grad_s^T = -div_s)
@@ -20,7 +19,7 @@
 //   lambda_j = lambda_u / h
 //   lambda^t_l = (1 - omega) mu_l + lambda_h + c_l . lambda_j
 //   g_kappa += -gamma phi(h) lambda_p          (FP64 accumulation)
-// and stores lambda^t_l(x) at x - c_l (the pre-shifted form for step t-1).
+// and stores lambda^t_l(x) for step t-1 (layout: AdjRec).
 // The forward moments h, j of step t come from the capture written by the
 // forward step; the film pressure and its gradient are recomputed from h.
 #include <cstring>
@@ -31,23 +30,42 @@
 
 namespace tflbm {
 
+// Adjoint state layout ("push in y, pull in x", as the forward records).
+// Records of kAdjW consecutive columns of one row, [ny][nstrips][RB]: the
+// nine segments of kAdjW values ordered by c_ly (kSlot), the record padded to
+// an odd number of 128-byte lines.  Entry l at (column X, row Y) holds
+// nu_l(X, Y) = lambda_l(X, Y + c_ly): a site stores its adjoint populations
+// at its own column, in the rows they are read from, so each strip writes
+// whole records of its own; the lane of column x takes
+// mu_l(x, y) = lambda_l(x + c_l) = nu_l(x + c_lx, y) from column x + c_lx
+// of row y.  dLoss/dkappa is FP64 in records of 64 values [ny][nstrips][64]:
+// the kAdjW columns and ten padding values, which the strip's halo lanes
+// write, so that the record is four whole lines.
+constexpr int kAdjW = 54;     // columns per strip and record
+constexpr int kAdjHalo = 5;   // halo columns per side: two per reverse step and the shift between two steps
+constexpr int kGkRB = 64 * 8;  // bytes of a dLoss/dkappa record
+constexpr int kDropOffset = 0x7fff0000;  // a buffer offset past every row: the access is dropped
+static_assert(kAdjW + 2 * kAdjHalo == 64, "a strip and its halo fill one wavefront");
+template <typename T> struct AdjRec {
+  static constexpr int SEG = kAdjW * (int)sizeof(T);
+  static constexpr int LINES = (9 * SEG + 127) / 128;
+  static constexpr int RB = (LINES % 2 ? LINES : LINES + 1) * 128;
+  __host__ __device__ static constexpr int seg(int l) { return kSlot[l] * SEG; }
+};
+
 struct AdjArgs {
-  const char *src;     // mu at the end of step t: [9][ny][ldx] in T
-  char *dst;           // mu at the end of step t-1
+  const char *src;     // adjoint records at the end of step t (AdjRec)
+  char *dst;           // adjoint records at the end of step t-1
   const char *cap;     // h, jx, jy of step t: capture records of the forward form
   const char *cap2;    // the same for step t-1 (two-step pass only)
   const void *kfield;  // kappa [ny][ldx] in T or nullptr
-  double *gk;          // dLoss/dkappa [ny][ldx] FP64
+  char *gk;            // dLoss/dkappa records [ny][nstrips][64] FP64
   int nx, ny, ldx;
   int cnblk;           // capture records per row (those of the forward step)
-  int64_t plane;
   int nstrips, H, ntiles, per_xcd;
   int n_exp, m_exp;
   double omega, gamma, nu, hstar, delta, ax, ay, g, kappa0;
 };
-
-constexpr int kAdjOutW = 60;   // one step: 64 lanes, one column each, two halo columns per side
-constexpr int kAdj2OutW = 54;  // two steps: five halo columns per side
 
 // The forward form whose capture records the reverse step reads (FP32 and
 // FP16S share the record geometry).
@@ -60,7 +78,7 @@ template <> struct CapForm<float> {
   static_assert(Form<kF16S>::B == Form<kF32>::B && cap_record_bytes<kF16S>() == cap_record_bytes<kF32>(),
                 "FP32 and FP16S capture records must agree");
 };
-int adj_columns_per_strip(int ns) { return ns == 2 ? kAdj2OutW : kAdjOutW; }
+int adj_record_columns() { return kAdjW; }
 
 // Lambda_F = 3 sum_l w_l c_l mu_l through differences of opposite populations.
 template <typename T>
@@ -93,21 +111,80 @@ template <typename T> struct AdjCoef {
         kap0((T)A.kappa0), cA((T)(3.0 * kW[1])), cD((T)(3.0 * kW[2])), n_exp(A.n_exp), m_exp(A.m_exp) {}
 };
 
-// h, j_x, j_y of one column, read from the capture records of a forward step.
-template <typename T> struct CapReader {
-  static constexpr int SEG = CapForm<T>::B * (int)sizeof(T);
-  const char *base;
-  size_t row_bytes;
-  __device__ CapReader(const char *cap, int cnblk, int col)
-      : base(cap + (size_t)(col / CapForm<T>::B) * CapForm<T>::CRB + (size_t)(col % CapForm<T>::B) * sizeof(T)),
-        row_bytes((size_t)cnblk * CapForm<T>::CRB) {}
-  __device__ __forceinline__ void read(int row, T &h, T &jx, T &jy) const {
-    const char *p = base + (size_t)row * row_bytes;
-    h = *(const T *)p;
-    jx = *(const T *)(p + SEG);
-    jy = *(const T *)(p + 2 * SEG);
+// Byte offsets of a lane inside one row of each array.  Rows are addressed
+// through a wave-uniform buffer resource, so the marching loop spends no
+// vector instructions on addresses.  Lane i of the strip starting at column
+// x0 holds column a = x0 - kAdjHalo + i (periodic).
+template <typename T> struct AdjLane {
+  int nu[3];  // adjoint entry of columns a - 1, a, a + 1 (by c_lx + 1)
+  int st;     // the lane's entry in its strip's record; kDropOffset for the halo lanes
+  int cap;    // capture entry of column a
+  int kap;    // kappa entry of column a
+  int gk;     // dLoss/dkappa entry (the halo lanes: the record's padding)
+  bool out;   // the lane's column belongs to the strip
+  __device__ AdjLane(const AdjArgs &A, int strip, int lane) {
+    const int x0 = strip * kAdjW, a = x0 - kAdjHalo + lane;
+    const int xend = min(x0 + kAdjW, A.nx);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int col = wrap(a + c - 1, A.nx);
+      const int s = col / kAdjW;
+      nu[c] = s * AdjRec<T>::RB + (col - s * kAdjW) * (int)sizeof(T);
+    }
+    out = a >= x0 && a < xend;
+    st = out ? strip * AdjRec<T>::RB + (a - x0) * (int)sizeof(T) : kDropOffset;
+    const int col = wrap(a, A.nx);
+    const int cb = col / CapForm<T>::B;
+    cap = cb * CapForm<T>::CRB + (col - cb * CapForm<T>::B) * (int)sizeof(T);
+    kap = col * (int)sizeof(T);
+    gk = strip * kGkRB + ((lane - kAdjHalo) & 63) * 8;
   }
 };
+
+template <typename T> __device__ __forceinline__ T ld_t(rsrc_t r, int off);
+template <> __device__ __forceinline__ float ld_t<float>(rsrc_t r, int off) { return ld_f32(r, off); }
+template <> __device__ __forceinline__ double ld_t<double>(rsrc_t r, int off) { return ld_f64(r, off); }
+
+// Row sizes in bytes.
+template <typename T> __device__ __forceinline__ uint32_t adj_row_bytes(const AdjArgs &A) {
+  return (uint32_t)A.nstrips * AdjRec<T>::RB;
+}
+template <typename T> __device__ __forceinline__ uint32_t cap_row_bytes(const AdjArgs &A) {
+  return (uint32_t)A.cnblk * CapForm<T>::CRB;
+}
+
+// mu_l of a row: nu_l(x + c_lx, row) from the adjoint records.
+template <typename T>
+__device__ __forceinline__ void load_mu(const AdjArgs &A, const AdjLane<T> &L, int row, T (&mu)[9]) {
+  const uint32_t rb = adj_row_bytes<T>(A);
+  const rsrc_t r = make_rsrc(A.src + (size_t)row * rb, rb);
+#pragma unroll
+  for (int l = 0; l < 9; ++l) mu[l] = ld_t<T>(r, L.nu[kCx[l] + 1] + AdjRec<T>::seg(l));
+}
+
+// h, j_x, j_y of a row from the capture records of a forward step.
+template <typename T>
+__device__ __forceinline__ void load_cap(const AdjArgs &A, const char *cap, const AdjLane<T> &L, int row, T &h, T &jx,
+                                         T &jy) {
+  constexpr int SEG = CapForm<T>::B * (int)sizeof(T);
+  const uint32_t rb = cap_row_bytes<T>(A);
+  const rsrc_t r = make_rsrc(cap + (size_t)row * rb, rb);
+  h = ld_t<T>(r, L.cap);
+  jx = ld_t<T>(r, L.cap + SEG);
+  jy = ld_t<T>(r, L.cap + 2 * SEG);
+}
+
+template <typename T>
+__device__ __forceinline__ T load_kap(const AdjArgs &A, const AdjLane<T> &L, int row) {
+  const uint32_t rb = (uint32_t)A.ldx * sizeof(T);
+  return ld_t<T>(make_rsrc((const char *)A.kfield + (size_t)row * rb, rb), L.kap);
+}
+
+// The resource of row y of the dLoss/dkappa records.
+__device__ __forceinline__ rsrc_t gk_row(const AdjArgs &A, int y) {
+  const uint32_t rb = (uint32_t)A.nstrips * kGkRB;
+  return make_rsrc(A.gk + (size_t)y * rb, rb);
+}
 
 // One reverse step as a machine over the rows of a strip, one column per
 // lane.  Rows enter in increasing y.  Once row r has entered (`push`), the
@@ -232,25 +309,26 @@ template <typename T> struct AdjStage {
   }
 };
 
-// Stores lambda^t_l of site (col, y) at (x - c_l, y - c_l), the pre-shifted
-// adjoint of the step before.
+// Stores lambda^t_l of row y: entry l of the lane's column goes to row
+// y - c_ly, where the step before reads it.  The halo lanes' stores are
+// dropped (kDropOffset), so a strip writes the contiguous entries of its
+// own records.
 template <typename T>
-__device__ __forceinline__ void store_pushed(const AdjArgs &A, int y, int col, int colW, int colE, const T (&lam)[9]) {
+__device__ __forceinline__ void store_lambda(const AdjArgs &A, const AdjLane<T> &L, int y, const T (&lam)[9]) {
+  const uint32_t rb = adj_row_bytes<T>(A);
   const int yN = (y + 1 == A.ny) ? 0 : y + 1;
   const int yS = (y == 0) ? A.ny - 1 : y - 1;
-  T *dst = (T *)A.dst;
+  // by c_ly + 1: c_ly = -1 -> row y + 1, 0 -> row y, +1 -> row y - 1
+  const rsrc_t rd[3] = {make_rsrc(A.dst + (size_t)yN * rb, rb), make_rsrc(A.dst + (size_t)y * rb, rb),
+                        make_rsrc(A.dst + (size_t)yS * rb, rb)};
 #pragma unroll
-  for (int l = 0; l < 9; ++l) {
-    const int cx = kCx[l], cy = kCy[l];
-    const int yd = cy == 0 ? y : (cy > 0 ? yS : yN);
-    const int xd = cx == 0 ? col : (cx > 0 ? colW : colE);
-    dst[(size_t)l * A.plane + (size_t)yd * A.ldx + xd] = lam[l];
-  }
+  for (int l = 0; l < 9; ++l) st_t(rd[kCy[l] + 1], L.st + AdjRec<T>::seg(l), lam[l]);
 }
 
-// One reverse step.  A workgroup is one wavefront marching down a strip of
-// kAdjOutW columns (plus two halo columns per side) over a chunk of rows; it
-// reads rows y0-2 .. yend+1 and writes rows y0 .. yend-1.
+// One reverse step.  A workgroup is one wavefront marching up a strip of
+// kAdjW columns (plus kAdjHalo halo columns per side, of which the stencils
+// of one step need two) over a chunk of rows; it reads rows y0-2 .. yend+1
+// and writes rows y0 .. yend-1.
 template <typename T, bool KF>
 __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
   const int b = blockIdx.x;
@@ -258,21 +336,12 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
   if (tile >= A.ntiles) return;
   const int strip = tile % A.nstrips;
   const int chunk = tile / A.nstrips;
-  const int x0 = strip * kAdjOutW;
   const int y0 = chunk * A.H;
   const int yend = min(y0 + A.H, A.ny);
-  const int xend = min(x0 + kAdjOutW, A.nx);
-  const int lane = threadIdx.x;
-  const int nx = A.nx, ny = A.ny, ldx = A.ldx;
-  const int64_t plane = A.plane;
-
-  const int a = x0 - 2 + lane;
-  const int col = wrap(a, nx), colE = wrap(a + 1, nx), colW = wrap(a - 1, nx);
-  const bool out = (a >= x0) && (a < xend);
+  const int ny = A.ny;
+  const AdjLane<T> L(A, strip, threadIdx.x);
 
   const AdjCoef<T> C(A);
-  const CapReader<T> cap(A.cap, A.cnblk, col);
-  const T *mu_src = (const T *)A.src;
   AdjStage<T> S;
   T mu1[9], mu2[9], mun[9];
   T hn, jxn, jyn, kn = C.kap0;
@@ -282,13 +351,12 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
   const int K = (yend - y0) + 4;
   int ry = wrap(y0 - 2, ny);
   auto load_row = [&](int row) {
-    const size_t o = (size_t)row * ldx + col;
-#pragma unroll
-    for (int l = 0; l < 9; ++l) mun[l] = mu_src[(size_t)l * plane + o];
-    cap.read(row, hn, jxn, jyn);
-    if constexpr (KF) kn = ((const T *)A.kfield)[o];
+    load_mu(A, L, row, mun);
+    load_cap(A, A.cap, L, row, hn, jxn, jyn);
+    if constexpr (KF) kn = load_kap(A, L, row);
   };
   load_row(ry);
+  double gkn = ld_f64(gk_row(A, y0), L.gk);  // dLoss/dkappa of the next output row
 
   for (int k = 0; k < K; ++k) {
     T mu0[9];
@@ -298,14 +366,17 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
     const int rn = (ry + 1 == ny) ? 0 : ry + 1;
     if (k + 1 < K) load_row(rn);
     S.push(mu0, h, jx, jy, kap, k >= 2, C);
-    if (k >= 4 && out) {
+    if (k >= 4) {
       // output row y = r-2
       const int y = y0 + (k - 4);
       T lam[9];
       double gt;
       S.out(mu2, lam, gt, C);
-      store_pushed(A, y, col, colW, colE, lam);
-      A.gk[(size_t)y * ldx + col] += gt;
+      store_lambda(A, L, y, lam);
+      double g = gkn;
+      if (k + 1 < K) gkn = ld_f64(gk_row(A, y + 1), L.gk);
+      if (L.out) g += gt;
+      st_f64(gk_row(A, y), L.gk, g);
     }
 #pragma unroll
     for (int l = 0; l < 9; ++l) {
@@ -325,7 +396,7 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
 // same row, so that g_kappa is read and written once per pass and receives
 // the two terms in the order of two single steps.  The workgroup is a single
 // wavefront, so the ring needs no barrier between wavefronts.  Strips are
-// kAdj2OutW columns plus five halo columns per side (two per stage plus the
+// kAdjW columns plus five halo columns per side (two per stage plus the
 // one-column shift between them); rows y0-5 .. yend+4 are read.
 template <typename T, bool KF>
 __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
@@ -336,23 +407,15 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
   if (tile >= A.ntiles) return;
   const int strip = tile % A.nstrips;
   const int chunk = tile / A.nstrips;
-  const int x0 = strip * kAdj2OutW;
   const int y0 = chunk * A.H;
   const int yend = min(y0 + A.H, A.ny);
-  const int xend = min(x0 + kAdj2OutW, A.nx);
   const int lane = threadIdx.x;
-  const int nx = A.nx, ny = A.ny, ldx = A.ldx;
-  const int64_t plane = A.plane;
-
-  const int a = x0 - 5 + lane;
-  const int col = wrap(a, nx), colE = wrap(a + 1, nx), colW = wrap(a - 1, nx);
-  const bool out = (a >= x0) && (a < xend);
+  const int ny = A.ny;
+  const AdjLane<T> L(A, strip, lane);
   // ring columns of x - 1 and x + 1 (the end lanes read themselves: halo)
   const int lw = lane > 0 ? lane - 1 : 0, le = lane < 63 ? lane + 1 : 63;
 
   const AdjCoef<T> C(A);
-  const CapReader<T> cap1(A.cap, A.cnblk, col), cap2(A.cap2, A.cnblk, col);
-  const T *mu_src = (const T *)A.src;
   AdjStage<T> S1, S2;
   T mu1[9], mu2[9], mun[9];
   T hn, jxn, jyn, kn = C.kap0;   // next input row of the step-t stage
@@ -369,14 +432,12 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
   int r1 = wrap(y0 - 5, ny);
   int r2 = wrap(y0 - 2, ny);
   auto load1 = [&](int row) {
-    const size_t o = (size_t)row * ldx + col;
-#pragma unroll
-    for (int l = 0; l < 9; ++l) mun[l] = mu_src[(size_t)l * plane + o];
-    cap1.read(row, hn, jxn, jyn);
-    if constexpr (KF) kn = ((const T *)A.kfield)[o];
+    load_mu(A, L, row, mun);
+    load_cap(A, A.cap, L, row, hn, jxn, jyn);
+    if constexpr (KF) kn = load_kap(A, L, row);
   };
-  auto load2 = [&](int row) { cap2.read(row, hm, jxm, jym); };
   load1(r1);
+  double gkn = ld_f64(gk_row(A, y0), L.gk);  // dLoss/dkappa of the next output row
 
   for (int k = 0; k < K; ++k) {
     T mu0[9];
@@ -390,7 +451,7 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
     const int r1n = (r1 + 1 == ny) ? 0 : r1 + 1;
     if (k + 1 < K) load1(r1n);
     if (k + 1 >= 6 && k + 1 < K) {
-      load2(r2);
+      load_cap(A, A.cap2, L, r2, hm, jxm, jym);
       r2 = (r2 + 1 == ny) ? 0 : r2 + 1;
     }
 
@@ -430,34 +491,38 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
         T lam[9];
         double gt;
         S2.out(mo, lam, gt, C);
-        if (out) {
-          store_pushed(A, y, col, colW, colE, lam);
-          double *gk = A.gk + (size_t)y * ldx + col;
-          double gsum = *gk;
-          gsum += gring[(k + 1) & 3][lane];  // the step-t term of row y, from iteration k-3
-          gsum += gt;
-          *gk = gsum;
+        store_lambda(A, L, y, lam);
+        double g = gkn;
+        if (k + 1 < K) gkn = ld_f64(gk_row(A, y + 1), L.gk);
+        if (L.out) {
+          g += gring[(k + 1) & 3][lane];  // the step-t term of row y, from iteration k-3
+          g += gt;
         }
+        st_f64(gk_row(A, y), L.gk, g);
       }
     }
   }
 }
 
-// mu_l(x) = dLoss/dh_N(x + c_l) for every l; g_kappa = 0.
+// nu_l(x, y) = lambda^N_l(x, y + c_ly) = dLoss/dh_N(x, y + c_ly) for every l
+// (h_N = sum_l f_l); dLoss/dkappa = 0, its padding included.  Thread i of a
+// row: entry i of the row's dLoss/dkappa records, and column i if i < nx.
 template <typename T>
 __global__ void adj_seed_kernel(AdjArgs A, const double *grad_h) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  if (x >= A.nx) return;
-  T *dst = (T *)A.dst;
+  if (i >= A.nstrips * 64) return;
+  ((double *)(A.gk + (size_t)y * A.nstrips * kGkRB))[i] = 0.0;
+  if (i >= A.nx) return;
+  const int s = i / kAdjW;
+  char *ent = A.dst + ((size_t)y * A.nstrips + s) * AdjRec<T>::RB + (size_t)(i - s * kAdjW) * sizeof(T);
   for (int l = 0; l < 9; ++l) {
-    const int xs = wrap(x + kCx[l], A.nx), ys = wrap(y + kCy[l], A.ny);
-    dst[(size_t)l * A.plane + (size_t)y * A.ldx + x] = (T)grad_h[(size_t)ys * A.nx + xs];
+    const int ys = wrap(y + kCy[l], A.ny);
+    *(T *)(ent + AdjRec<T>::seg(l)) = (T)grad_h[(size_t)ys * A.nx + i];
   }
-  A.gk[(size_t)y * A.ldx + x] = 0.0;
 }
 
-// dLoss/dh0 = sum_l lambda^0_l dE_l/dh0 with lambda^0_l(x) = mu_l(x - c_l);
+// dLoss/dh0 = sum_l lambda^0_l dE_l/dh0 with lambda^0_l(x, y) = nu_l(x, y - c_ly);
 // dLoss/dtheta = dLoss/dkappa * (n-1)(m-1)/((n-m) h_*) * sin(theta).
 template <typename T>
 __global__ void adj_finish_kernel(AdjArgs A, const double *h0, const double *theta, double theta0, double kconst,
@@ -466,13 +531,14 @@ __global__ void adj_finish_kernel(AdjArgs A, const double *h0, const double *the
   const int y = blockIdx.y;
   if (x >= A.nx) return;
   const size_t od = (size_t)y * A.nx + x;
-  const T *src = (const T *)A.src;
+  const int st = x / kAdjW, pos = x - st * kAdjW;
   if (grad_h0) {
     const double h = h0[od];
+    const size_t ent = (size_t)st * AdjRec<T>::RB + (size_t)pos * sizeof(T);
     double s = 0.0;
     for (int l = 0; l < 9; ++l) {
-      const int xs = wrap(x - kCx[l], A.nx), ys = wrap(y - kCy[l], A.ny);
-      const double lam = (double)src[(size_t)l * A.plane + (size_t)ys * A.ldx + xs];
+      const int ys = wrap(y - kCy[l], A.ny);
+      const double lam = (double)*(const T *)(A.src + (size_t)ys * A.nstrips * AdjRec<T>::RB + ent + AdjRec<T>::seg(l));
       const double dE = l == 0 ? 1.0 - A.g * h * (5.0 / 3.0) : ((l & 1) ? A.g * h / 3.0 : A.g * h / 12.0);
       s += lam * dE;
     }
@@ -480,7 +546,8 @@ __global__ void adj_finish_kernel(AdjArgs A, const double *h0, const double *the
   }
   if (grad_theta) {
     const double th = theta ? theta[od] : theta0;
-    grad_theta[od] = A.gk[(size_t)y * A.ldx + x] * kconst * sin(th);
+    const double gk = ((const double *)(A.gk + ((size_t)y * A.nstrips + st) * kGkRB))[pos];
+    grad_theta[od] = gk * kconst * sin(th);
   }
 }
 
@@ -519,7 +586,7 @@ int adj_blocks_per_cu(int prec, bool kf, int ns) {
 }
 
 hipError_t launch_adj_seed(int prec, const AdjArgs &B, const double *grad_h, hipStream_t s) {
-  const dim3 block(256), grid((B.nx + 255) / 256, B.ny);
+  const dim3 block(256), grid((B.nstrips * 64 + 255) / 256, B.ny);
   if (prec == kF64) adj_seed_kernel<double><<<grid, block, 0, s>>>(B, grad_h);
   else adj_seed_kernel<float><<<grid, block, 0, s>>>(B, grad_h);
   return hipGetLastError();
@@ -535,7 +602,11 @@ hipError_t launch_adj_finish(int prec, const AdjArgs &B, const double *h0, const
   return hipGetLastError();
 }
 
-static size_t adj_buf_bytes(const tflbm_sim *s) { return 9 * (size_t)s->plane * work_bytes(s->p.prec); }
+static size_t adj_buf_bytes(const tflbm_sim *s) {
+  const size_t rb = s->p.prec == kF64 ? AdjRec<double>::RB : AdjRec<float>::RB;
+  return (size_t)s->p.ny * s->adj_nstrips * rb;
+}
+static size_t gk_bytes(const tflbm_sim *s) { return (size_t)s->p.ny * s->adj_nstrips * kGkRB; }
 static size_t round4k(size_t v) { return (v + 4095) / 4096 * 4096; }
 
 // AdjArgs of the current adjoint buffers, shaped for `ns` steps per pass.
@@ -546,14 +617,13 @@ static AdjArgs make_adj_args(const tflbm_sim *s, void *d_adj, int ns = 1) {
   const size_t nb = round4k(adj_buf_bytes(s));
   B.src = base + (s->adj_cur == 0 ? 0 : nb);
   B.dst = base + (s->adj_cur == 0 ? nb : 0);
-  B.gk = (double *)(base + 2 * nb);
+  B.gk = base + 2 * nb;
   B.kfield = s->kfield == kKappa ? (const void *)(s->ws + s->off_k) : nullptr;
   B.nx = s->p.nx;
   B.ny = s->p.ny;
   B.ldx = s->ldx;
   B.cnblk = s->nblk;
-  B.plane = s->plane;
-  B.nstrips = ns == 2 ? s->adj2_nstrips : s->adj_nstrips;
+  B.nstrips = s->adj_nstrips;  // the record columns of the adjoint state; both kernels march them
   B.H = ns == 2 ? s->adj2_rows : s->adj_rows;
   B.ntiles = ns == 2 ? s->adj2_ntiles : s->adj_ntiles;
   B.per_xcd = ns == 2 ? s->adj2_per_xcd : s->adj_per_xcd;
@@ -579,7 +649,7 @@ extern "C" {
 
 size_t tflbm_adj_bytes(const tflbm_sim *sim) {
   if (!sim) return 0;
-  return 2 * round4k(adj_buf_bytes(sim)) + round4k(8 * (size_t)sim->plane);
+  return 2 * round4k(adj_buf_bytes(sim)) + round4k(gk_bytes(sim));
 }
 
 int tflbm_adj_seed(tflbm_sim *sim, void *d_adj, const double *d_grad_h, tflbm_stream_t stream) {

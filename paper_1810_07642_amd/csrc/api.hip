@@ -118,8 +118,8 @@ void plan_launches(tflbm_sim *s) {
   s->adj_rows = choose_rows(ny, s->adj_nstrips, aocc1 * cus, kMinRowsAdj, "TFLBM_ADJ_ROWS");
   s->adj_ntiles = s->adj_nstrips * ((ny + s->adj_rows - 1) / s->adj_rows);
   s->adj_per_xcd = (s->adj_ntiles + 7) / 8;
-  s->adj2_rows = choose_rows(ny, s->adj2_nstrips, aocc2 * cus, kMinRowsAdj2, "TFLBM_ADJ_ROWS2");
-  s->adj2_ntiles = s->adj2_nstrips * ((ny + s->adj2_rows - 1) / s->adj2_rows);
+  s->adj2_rows = choose_rows(ny, s->adj_nstrips, aocc2 * cus, kMinRowsAdj2, "TFLBM_ADJ_ROWS2");
+  s->adj2_ntiles = s->adj_nstrips * ((ny + s->adj2_rows - 1) / s->adj2_rows);
   s->adj2_per_xcd = (s->adj2_ntiles + 7) / 8;
   // Two reverse steps per pass pay off once the lattice fills the GPU: with
   // fewer tiles of the shortest chunk than resident slots, a tile's time is
@@ -127,7 +127,7 @@ void plan_launches(tflbm_sim *s) {
   // stages per row) than two single passes (four halo rows each).  Measured
   // at FP32: single steps win at 512^2 (11.2 vs 11.9 us per step), the fused
   // pass from 768^2 on (14.8 vs 15.5; 4096^2: 281 vs 477).
-  s->adj_fuse_fits = (int64_t)s->adj2_nstrips * ((ny + kMinRowsAdj2 - 1) / kMinRowsAdj2) > (int64_t)aocc2 * cus;
+  s->adj_fuse_fits = (int64_t)s->adj_nstrips * ((ny + kMinRowsAdj2 - 1) / kMinRowsAdj2) > (int64_t)aocc2 * cus;
   s->graphs = (int64_t)s->p.nx * ny <= kGraphMaxSites;
   if (const char *e = std::getenv("TFLBM_GRAPH")) s->graphs = std::atoi(e) != 0;
 }
@@ -271,8 +271,7 @@ int tflbm_create(const tflbm_params *p, tflbm_sim **out) {
     s->fuse = f <= 1 ? 1 : (f >= 3 ? 3 : 2);
   }
   if (const char *e = std::getenv("TFLBM_ADJ_FUSE")) s->adj_fuse = std::atoi(e) == 1 ? 1 : 2;  // default 0: by lattice size
-  s->adj_nstrips = (p->nx + adj_columns_per_strip(1) - 1) / adj_columns_per_strip(1);
-  s->adj2_nstrips = (p->nx + adj_columns_per_strip(2) - 1) / adj_columns_per_strip(2);
+  s->adj_nstrips = (p->nx + adj_record_columns() - 1) / adj_record_columns();
   *out = s;
   return TFLBM_OK;
 }

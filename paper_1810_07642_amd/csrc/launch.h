@@ -38,7 +38,7 @@ hipError_t launch_adj_seed(int prec, const AdjArgs &B, const double *grad_h, hip
 hipError_t launch_adj_step(int prec, const AdjArgs &B, bool kfield, int ns, hipStream_t s);
 hipError_t launch_adj_finish(int prec, const AdjArgs &B, const double *h0, const double *theta, double theta0,
                              double kconst, double *grad_h0, double *grad_theta, hipStream_t s);
-int adj_columns_per_strip(int ns);
+int adj_record_columns();
 int adj_blocks_per_cu(int prec, bool kfield, int ns);
 
 }  // namespace tflbm

@@ -36,8 +36,9 @@ struct tflbm_sim {
   // reverse pass
   int adj_cur = 0;        // 0: first adjoint buffer holds the current adjoint
   bool adj_seeded = false;
-  int adj_rows = 0, adj_nstrips = 0, adj_ntiles = 0, adj_per_xcd = 0;      // one step per pass
-  int adj2_rows = 0, adj2_nstrips = 0, adj2_ntiles = 0, adj2_per_xcd = 0;  // two steps per pass
+  int adj_nstrips = 0;    // strips of the adjoint records (both reverse kernels march them)
+  int adj_rows = 0, adj_ntiles = 0, adj_per_xcd = 0;      // one step per pass
+  int adj2_rows = 0, adj2_ntiles = 0, adj2_per_xcd = 0;   // two steps per pass
   int adj_fuse = 0;       // reverse steps per pass: 1, 2 (when possible), 0 = 2 if adj_fuse_fits
   bool adj_fuse_fits = false;  // the lattice fills the GPU with two-step tiles
   mutable std::string last_error;

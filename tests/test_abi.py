@@ -83,7 +83,6 @@ def test_workspace_and_state_sizes(lib, prec, per_site):
     p = params(lib, prec=prec, nx=100, ny=30)
     h = ctypes.c_void_p()
     assert lib.tflbm_create(ctypes.byref(p), ctypes.byref(h)) == 0
-    ldx = 128
     B, RB = RECORDS[prec]
     nblk = -(-100 // B)
     assert lib.tflbm_state_bytes(h) == 30 * nblk * RB
@@ -92,7 +91,14 @@ def test_workspace_and_state_sizes(lib, prec, per_site):
     wb = 8 if prec == 0 else 4
     # capture: records of the same B columns, three segments padded to whole lines
     assert lib.tflbm_capture_bytes(h) == 30 * nblk * (-(-3 * B * wb // 128) * 128)
-    assert lib.tflbm_adj_bytes(h) >= 2 * 9 * wb * ldx * 30 + 8 * ldx * 30
+    # adjoint: two buffers of records of 54 columns (nine segments padded to an
+    # odd number of lines) and FP64 dLoss/dkappa records of 64 values, each
+    # rounded to 4 KiB
+    ARB = {0: 31 * 128, 1: 17 * 128, 2: 17 * 128}[prec]
+    assert ARB >= 9 * 54 * wb
+    nas = -(-100 // 54)
+    r4k = lambda v: -(-v // 4096) * 4096
+    assert lib.tflbm_adj_bytes(h) == 2 * r4k(30 * nas * ARB) + r4k(30 * nas * 512)
     from paper_1810_07642_amd.sim import capture_bytes_for
     assert capture_bytes_for(100, 30, {0: "fp64", 1: "fp32", 2: "fp16s"}[prec]) == lib.tflbm_capture_bytes(h)
     lib.tflbm_destroy(h)
