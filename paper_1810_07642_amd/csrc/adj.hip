@@ -141,6 +141,16 @@ template <typename T> struct AdjLane {
   }
 };
 
+// One input row of a reverse stage: the adjoint read (mu) and the forward
+// moments and kappa of the same row.
+template <typename T> struct AdjIn {
+  T mu[9];
+  T h, jx, jy, kap;
+};
+template <typename T> struct AdjCap {
+  T h, jx, jy;
+};
+
 template <typename T> __device__ __forceinline__ T ld_t(rsrc_t r, int off);
 template <> __device__ __forceinline__ float ld_t<float>(rsrc_t r, int off) { return ld_f32(r, off); }
 template <> __device__ __forceinline__ double ld_t<double>(rsrc_t r, int off) { return ld_f64(r, off); }
@@ -417,9 +427,7 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
 
   const AdjCoef<T> C(A);
   AdjStage<T> S1, S2;
-  T mu1[9], mu2[9], mun[9];
-  T hn, jxn, jyn, kn = C.kap0;   // next input row of the step-t stage
-  T hm = 0, jxm = 0, jym = 0;    // next input row of the step-(t-1) stage
+  T mu1[9], mu2[9];
   // kappa of the step-t input rows of the last three iterations: the
   // step-(t-1) stage takes each row three iterations later
   T kd1 = C.kap0, kd2 = C.kap0, kd3 = C.kap0;
@@ -427,33 +435,34 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
   for (int l = 0; l < 9; ++l) mu1[l] = mu2[l] = 0;
 
   // iteration k: step-t input row y0-5+k, step-t output row y0-7+k (k >= 4),
-  // step-(t-1) input row y0-8+k (k >= 6), step-(t-1) output row y0-10+k (k >= 10)
+  // step-(t-1) input row y0-8+k (k >= 6), step-(t-1) output row y0-10+k (k >= 10).
+  // Input rows are loaded two iterations ahead, into the buffers the
+  // iteration two back consumed (ia/ca for even k, ib/cb for odd k).
   const int K = (yend - y0) + 10;
-  int r1 = wrap(y0 - 5, ny);
-  int r2 = wrap(y0 - 2, ny);
-  auto load1 = [&](int row) {
-    load_mu(A, L, row, mun);
-    load_cap(A, A.cap, L, row, hn, jxn, jyn);
-    if constexpr (KF) kn = load_kap(A, L, row);
+  AdjIn<T> ia, ib;
+  AdjCap<T> ca = {}, cb = {};
+  auto load1 = [&](int k, AdjIn<T> &in) {
+    const int row = wrap(y0 - 5 + k, ny);
+    load_mu(A, L, row, in.mu);
+    load_cap(A, A.cap, L, row, in.h, in.jx, in.jy);
+    in.kap = C.kap0;
+    if constexpr (KF) in.kap = load_kap(A, L, row);
   };
-  load1(r1);
+  load1(0, ia);
+  load1(1, ib);
   double gkn = ld_f64(gk_row(A, y0), L.gk);  // dLoss/dkappa of the next output row
 
-  for (int k = 0; k < K; ++k) {
+  auto iteration = [&](int k, AdjIn<T> &in, AdjCap<T> &cin) {
     T mu0[9];
 #pragma unroll
-    for (int l = 0; l < 9; ++l) mu0[l] = mun[l];
-    const T h = hn, jx = jxn, jy = jyn, kap = kn;
-    const T h_2 = hm, jx_2 = jxm, jy_2 = jym, kap_2 = kd3;
+    for (int l = 0; l < 9; ++l) mu0[l] = in.mu[l];
+    const T h = in.h, jx = in.jx, jy = in.jy, kap = in.kap;
+    const T h_2 = cin.h, jx_2 = cin.jx, jy_2 = cin.jy, kap_2 = kd3;
     kd3 = kd2;
     kd2 = kd1;
     kd1 = kap;
-    const int r1n = (r1 + 1 == ny) ? 0 : r1 + 1;
-    if (k + 1 < K) load1(r1n);
-    if (k + 1 >= 6 && k + 1 < K) {
-      load_cap(A, A.cap2, L, r2, hm, jxm, jym);
-      r2 = (r2 + 1 == ny) ? 0 : r2 + 1;
-    }
+    if (k + 2 < K) load1(k + 2, in);
+    if (k + 2 >= 6 && k + 2 < K) load_cap(A, A.cap2, L, wrap(y0 - 6 + k, ny), cin.h, cin.jx, cin.jy);
 
     S1.push(mu0, h, jx, jy, kap, k >= 2, C);
     if (k >= 4) {
@@ -470,7 +479,6 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
       mu2[l] = mu1[l];
       mu1[l] = mu0[l];
     }
-    r1 = r1n;
 
     if (k >= 6) {
       __syncthreads();
@@ -501,7 +509,13 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
         st_f64(gk_row(A, y), L.gk, g);
       }
     }
+  };
+  int k = 0;
+  for (; k + 1 < K; k += 2) {
+    iteration(k, ia, ca);
+    iteration(k + 1, ib, cb);
   }
+  if (k < K) iteration(k, ia, ca);
 }
 
 // nu_l(x, y) = lambda^N_l(x, y + c_ly) = dLoss/dh_N(x, y + c_ly) for every l

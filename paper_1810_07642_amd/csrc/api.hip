@@ -125,8 +125,10 @@ void plan_launches(tflbm_sim *s) {
   // fewer tiles of the shortest chunk than resident slots, a tile's time is
   // its chain of rows, which the fused pass makes longer (ten halo rows, two
   // stages per row) than two single passes (four halo rows each).  Measured
-  // at FP32: single steps win at 512^2 (11.2 vs 11.9 us per step), the fused
-  // pass from 768^2 on (14.8 vs 15.5; 4096^2: 281 vs 477).
+  // per step at FP32: single steps win up to 512^2 (10.2 vs 11.2 us), the
+  // fused pass from 768^2 on (15.6 vs 20.1; 4096^2: 256 vs 446); at FP64 the
+  // two tie at 512^2 (16.9 us) and the fused pass wins from 768^2 on (25.9
+  // vs 31.8).
   s->adj_fuse_fits = (int64_t)s->adj_nstrips * ((ny + kMinRowsAdj2 - 1) / kMinRowsAdj2) > (int64_t)aocc2 * cus;
   s->graphs = (int64_t)s->p.nx * ny <= kGraphMaxSites;
   if (const char *e = std::getenv("TFLBM_GRAPH")) s->graphs = std::atoi(e) != 0;
