@@ -104,6 +104,31 @@ def make_sim(prec, p, h0, th, fuse=None, href=None):
         os.environ.pop("TFLBM_FUSE", None)
 
 
+def general_stages(sims, p, h0, th, ceil_gbs):
+    """The same workload and state with the general collision stages
+    (TFLBM_OMEGA1=0: the stages that keep the populations, as any tau != 1
+    needs; two steps per pass): what the step costs when tau != 1."""
+    import torch
+    out = {}
+    sites = h0.numel()
+    for prec in ("fp64", "fp32", "fp16s"):
+        os.environ["TFLBM_OMEGA1"] = "0"
+        try:
+            sim = make_sim(prec, p, h0, th)
+        finally:
+            os.environ.pop("TFLBM_OMEGA1", None)
+        sim.state_load(sims[prec].state_save(), sims[prec].steps)
+        ms = timed_steps(sim, EXTRA_STEPS, 20)
+        sim.check()
+        spp = sim.steps_per_pass
+        out[prec] = {"mlups": round(sites * EXTRA_STEPS / (ms * 1e-3) / 1e6, 1), "steps_per_pass": spp,
+                     "roofline_frac": roofline_block("general stages", BYTES_PER_SITE[prec] * sites,
+                                                     ms / launches(EXTRA_STEPS, spp), None, ceil_gbs)["frac"]}
+        del sim
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_form(prec, p, h0, th, steps, warmup, fuse=None, href=None):
     import torch
     sim = make_sim(prec, p, h0, th, fuse, href)
@@ -114,10 +139,15 @@ def run_form(prec, p, h0, th, steps, warmup, fuse=None, href=None):
     return ms
 
 
-def launches(steps):
-    """Launches of the step kernel for `steps` steps on a lattice that runs
-    fused pairs (an odd count ends with one single step)."""
-    return steps // 2 + steps % 2
+def launches(steps, per_pass):
+    """Launches of the step kernel for `steps` steps with at most `per_pass`
+    steps per pass (the last pass may be shorter)."""
+    return -(-steps // per_pass)
+
+
+def step_kernel_name(sim, prec):
+    spp = sim.steps_per_pass
+    return f"step_kernel<{prec}, kappa field, {spp} fused steps{', omega = 1 stages' if sim.params.tau == 1.0 else ''}>"
 
 
 def roofline_block(kernel, bytes_per_launch, launch_ms, traffic, ceiling_gbs, steps_per_launch=2):
@@ -456,9 +486,10 @@ def main():
     sims["fp64"].check()
     ms_step = ms64 / args.steps
     mlups = sites * args.steps / (ms64 * 1e-3) / 1e6
-    launch_ms = ms64 / launches(args.steps)
-    roof = roofline_block("step_kernel<fp64, kappa field, 2 fused steps>", BYTES_PER_SITE["fp64"] * sites,
-                          launch_ms, committed_traffic("fp64"), ceil_gbs)
+    spp64 = sims["fp64"].steps_per_pass
+    launch_ms = ms64 / launches(args.steps, spp64)
+    roof = roofline_block(step_kernel_name(sims["fp64"], "fp64"), BYTES_PER_SITE["fp64"] * sites,
+                          launch_ms, committed_traffic("fp64"), ceil_gbs, steps_per_launch=spp64)
     roof["per_step_equivalent_GBps"] = round(BYTES_PER_SITE["fp64"] * sites / (ms_step * 1e-3) / 1e9, 1)
     line = {
         "metric": "D2Q9 thin-film MLUPS, % HBM roofline, FP32/FP64 speedup, adjoint/forward time",
@@ -489,22 +520,26 @@ def main():
             ms = timed_steps(sims[prec], EXTRA_STEPS, 50)
             sims[prec].check()
             ml = sites * EXTRA_STEPS / (ms * 1e-3) / 1e6
-            lm = ms / launches(EXTRA_STEPS)
+            spp = sims[prec].steps_per_pass
+            lm = ms / launches(EXTRA_STEPS, spp)
             forms[prec] = {"mlups": round(ml, 1), "ms_per_step": round(ms / EXTRA_STEPS, 5),
-                           "steps_timed": EXTRA_STEPS, "href": HREF[prec],
-                           "roofline": roofline_block(f"step_kernel<{prec}, kappa field, 2 fused steps>",
+                           "steps_timed": EXTRA_STEPS, "href": HREF[prec], "steps_per_pass": spp,
+                           "roofline": roofline_block(step_kernel_name(sims[prec], prec),
                                                       BYTES_PER_SITE[prec] * sites, lm, committed_traffic(prec),
-                                                      ceil_gbs)}
+                                                      ceil_gbs, steps_per_launch=spp)}
             forms[prec]["roofline"]["per_step_equivalent_GBps"] = round(
                 BYTES_PER_SITE[prec] * sites / (ms / EXTRA_STEPS * 1e-3) / 1e9, 1)
         for prec in ("fp32", "fp16s"):
             forms[prec]["speedup_over_fp64"] = round(forms[prec]["mlups"] / forms["fp64"]["mlups"], 3)
         extras["forms"] = forms
+        extras["general_collision_stages"] = general_stages(sims, p, h0, th, ceil_gbs)
         extras["timing_starts_after_steps"] = ACCURACY_STEPS
         del sims
         torch.cuda.empty_cache()
-        log("forms: " + ", ".join(f"{k} {v['mlups']:.0f} MLUPS (pass frac {v['roofline']['frac']:.3f})"
-                                  for k, v in forms.items()))
+        log("forms: " + ", ".join(f"{k} {v['mlups']:.0f} MLUPS ({v['steps_per_pass']} steps per pass, "
+                                  f"pass frac {v['roofline']['frac']:.3f})" for k, v in forms.items()))
+        log("general stages (tau != 1): " + ", ".join(f"{k} {v['mlups']:.0f} MLUPS"
+                                                      for k, v in extras["general_collision_stages"].items()))
         s1 = make_sim("fp32", p, h0, th, fuse=1)
         s1.step(ACCURACY_STEPS)
         ms1 = timed_steps(s1, EXTRA_STEPS, 20)

@@ -126,11 +126,15 @@ int tflbm_check_params(const tflbm_params *p);
  * does not prevent creation.  *out receives the handle or NULL.
  * Launch-shape overrides, read from the environment here (fusion) and at
  * tflbm_init (row chunks), for measurement only; results do not depend on
- * them: TFLBM_FUSE=1 or 2 (one or two forward steps per pass in tflbm_step
- * and tflbm_step_capture), TFLBM_ADJ_FUSE=1 or 2 (the same for the reverse
- * steps of tflbm_adj_steps; by default two where the lattice is large enough
- * for it to pay), TFLBM_ROWS, TFLBM_ROWS2, TFLBM_ADJ_ROWS,
- * TFLBM_ADJ_ROWS2 (rows per chunk of the one- and two-step kernels),
+ * them: TFLBM_FUSE=1, 2 or 3 (most forward steps per pass in tflbm_step;
+ * tflbm_step_capture runs at most two; by default three with tau = 1 on
+ * large lattices, else two where the lattice is large enough for it to pay),
+ * TFLBM_OMEGA1=0 (with tau = 1, the general collision stages instead of the
+ * ones that keep no populations; the same bits), TFLBM_ADJ_FUSE=1 or 2 (the
+ * same for the reverse steps of tflbm_adj_steps; by default two where the
+ * lattice is large enough for it to pay), TFLBM_ROWS, TFLBM_ROWS2,
+ * TFLBM_ROWS3, TFLBM_ADJ_ROWS, TFLBM_ADJ_ROWS2 (rows per chunk of the one-,
+ * two- and three-step kernels),
  * TFLBM_GRAPH=0 or 1 (read at tflbm_init: whether tflbm_step replays blocks
  * of steps from graphs; by default on lattices of at most 2^20 sites). */
 int tflbm_create(const tflbm_params *p, tflbm_sim **out);
@@ -190,6 +194,12 @@ int tflbm_step(tflbm_sim *sim, int64_t nsteps, tflbm_stream_t stream);
 /* Number of step graphs the handle holds (0, 1 or 2: one per starting buffer
  * parity of a block); -1 for NULL. */
 int tflbm_step_graphs(const tflbm_sim *sim);
+
+/* Most time steps one pass of tflbm_step advances on this handle (1, 2 or 3:
+ * several steps of eq. "LBE" applied to a row chunk before it is stored; 3
+ * needs tau = 1 and a lattice large enough for it to pay; TFLBM_FUSE
+ * overrides); EINVAL for NULL, ESTATE before tflbm_init. */
+int tflbm_steps_per_pass(const tflbm_sim *sim);
 
 /* Number of steps taken since tflbm_init (host counter). */
 int64_t tflbm_step_count(const tflbm_sim *sim);

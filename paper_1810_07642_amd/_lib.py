@@ -54,6 +54,7 @@ SIGNATURES = {
     "tflbm_step": (_int, [_vp, _i64, _vp]),
     "tflbm_step_count": (_i64, [_vp]),
     "tflbm_step_graphs": (_int, [_vp]),
+    "tflbm_steps_per_pass": (_int, [_vp]),
     "tflbm_read": (_int, [_vp, _dp, _dp, _dp, _vp]),
     "tflbm_mass": (_int, [_vp, ctypes.POINTER(ctypes.c_double), _vp]),
     "tflbm_mass_noalloc": (_int, [_vp, _dp, _vp]),

@@ -62,22 +62,12 @@ struct AdjArgs {
   char *gk;            // dLoss/dkappa records [ny][nstrips][64] FP64
   int nx, ny, ldx;
   int cnblk;           // capture records per row (those of the forward step)
+  int capB, capRB;     // sites and bytes per capture record (the forward form's)
   int nstrips, H, ntiles, per_xcd;
   int n_exp, m_exp;
   double omega, gamma, nu, hstar, delta, ax, ay, g, kappa0;
 };
 
-// The forward form whose capture records the reverse step reads (FP32 and
-// FP16S share the record geometry).
-template <typename T> struct CapForm;
-template <> struct CapForm<double> {
-  static constexpr int B = Form<kF64>::B, CRB = cap_record_bytes<kF64>();
-};
-template <> struct CapForm<float> {
-  static constexpr int B = Form<kF32>::B, CRB = cap_record_bytes<kF32>();
-  static_assert(Form<kF16S>::B == Form<kF32>::B && cap_record_bytes<kF16S>() == cap_record_bytes<kF32>(),
-                "FP32 and FP16S capture records must agree");
-};
 int adj_record_columns() { return kAdjW; }
 
 // Lambda_F = 3 sum_l w_l c_l mu_l through differences of opposite populations.
@@ -134,8 +124,8 @@ template <typename T> struct AdjLane {
     out = a >= x0 && a < xend;
     st = out ? strip * AdjRec<T>::RB + (a - x0) * (int)sizeof(T) : kDropOffset;
     const int col = wrap(a, A.nx);
-    const int cb = col / CapForm<T>::B;
-    cap = cb * CapForm<T>::CRB + (col - cb * CapForm<T>::B) * (int)sizeof(T);
+    const int cb = col / A.capB;
+    cap = cb * A.capRB + (col - cb * A.capB) * (int)sizeof(T);
     kap = col * (int)sizeof(T);
     gk = strip * kGkRB + ((lane - kAdjHalo) & 63) * 8;
   }
@@ -159,9 +149,7 @@ template <> __device__ __forceinline__ double ld_t<double>(rsrc_t r, int off) { 
 template <typename T> __device__ __forceinline__ uint32_t adj_row_bytes(const AdjArgs &A) {
   return (uint32_t)A.nstrips * AdjRec<T>::RB;
 }
-template <typename T> __device__ __forceinline__ uint32_t cap_row_bytes(const AdjArgs &A) {
-  return (uint32_t)A.cnblk * CapForm<T>::CRB;
-}
+__device__ __forceinline__ uint32_t cap_row_bytes(const AdjArgs &A) { return (uint32_t)A.cnblk * A.capRB; }
 
 // mu_l of a row: nu_l(x + c_lx, row) from the adjoint records.
 template <typename T>
@@ -176,8 +164,8 @@ __device__ __forceinline__ void load_mu(const AdjArgs &A, const AdjLane<T> &L, i
 template <typename T>
 __device__ __forceinline__ void load_cap(const AdjArgs &A, const char *cap, const AdjLane<T> &L, int row, T &h, T &jx,
                                          T &jy) {
-  constexpr int SEG = CapForm<T>::B * (int)sizeof(T);
-  const uint32_t rb = cap_row_bytes<T>(A);
+  const int SEG = A.capB * (int)sizeof(T);
+  const uint32_t rb = cap_row_bytes(A);
   const rsrc_t r = make_rsrc(cap + (size_t)row * rb, rb);
   h = ld_t<T>(r, L.cap);
   jx = ld_t<T>(r, L.cap + SEG);
@@ -637,6 +625,8 @@ static AdjArgs make_adj_args(const tflbm_sim *s, void *d_adj, int ns = 1) {
   B.ny = s->p.ny;
   B.ldx = s->ldx;
   B.cnblk = s->nblk;
+  B.capB = record_sites(s->p.prec);
+  B.capRB = capture_record_bytes(s->p.prec);
   B.nstrips = s->adj_nstrips;  // the record columns of the adjoint state; both kernels march them
   B.H = ns == 2 ? s->adj2_rows : s->adj_rows;
   B.ntiles = ns == 2 ? s->adj2_ntiles : s->adj_ntiles;

@@ -46,6 +46,18 @@ int choose_rows(int ny, int nstrips, int slots, int min_rows, const char *env_na
 constexpr int kMinRowsStep = 1;
 constexpr int kMinRowsAdj = 1;
 constexpr int kMinRowsAdj2 = 4;
+// Three fused steps per pass (omega = 1) are planned once the lattice gives
+// every resident slot of the three-step kernel at least this many strip
+// rows: below that a tile's sixteen halo rows and longer chain of rows cost
+// more than the third of the bytes they save.  Measured (MLUPS, two / three
+// steps per pass; strip rows per slot): FP64 768^2 37.4k / 36.0k (6.4),
+// 1024^2 43.2k / 46.8k (11.5), 2048^2 51.0k / 64.5k, 4096^2 55.4k / 73.5k;
+// FP32 1024^2 69.6k / 66.6k (5.0), 1536^2 92.1k / 106.4k (11.3), 2048^2
+// 98.9k / 124.2k, 4096^2 108.1k / 153.1k.  With the general stages the three
+// steps' population histories cap a CU at five wavefronts, and two steps per
+// pass are as fast or faster (FP64 4096^2 54.8k / 52.7k, FP32 107.2k /
+// 108.3k, 2048^2 97.6k / 91.3k).
+constexpr int kFuse3MinRowsPerSlot = 8;
 
 // Lattices up to this many sites have steps bound by launch latency and a
 // chain of rows, not by bytes: tflbm_step replays blocks of kGraphSteps steps
@@ -73,8 +85,8 @@ void plan_launches(tflbm_sim *s) {
   }
   const int ny = s->p.ny;
   const bool g0 = s->p.g == 0.0;
-  int occ1 = step_blocks_per_cu(s->p.prec, s->kfield, 1, g0);
-  int occ2 = step_blocks_per_cu(s->p.prec, s->kfield, 2, g0);
+  int occ1 = step_blocks_per_cu(s->p.prec, s->kfield, 1, g0, s->w1);
+  int occ2 = step_blocks_per_cu(s->p.prec, s->kfield, 2, g0, s->w1);
   if (occ1 <= 0) occ1 = 8;
   if (occ2 <= 0) occ2 = 8;
   s->rows = choose_rows(ny, s->nstrips, occ1 * cus, kMinRowsStep, "TFLBM_ROWS");
@@ -92,7 +104,7 @@ void plan_launches(tflbm_sim *s) {
   s->rows2 = choose_rows(ny, s->nstrips, plan2 * cus, kMinRowsStep, "TFLBM_ROWS2");
   s->ntiles2 = s->nstrips * ((ny + s->rows2 - 1) / s->rows2);
   s->per_xcd2 = (s->ntiles2 + 7) / 8;
-  int occ3 = step_blocks_per_cu(s->p.prec, s->kfield, 3, g0);
+  int occ3 = step_blocks_per_cu(s->p.prec, s->kfield, 3, g0, s->w1);
   if (occ3 <= 0) occ3 = 5;
   s->rows3 = choose_rows(ny, s->nstrips, occ3 * cus, kMinRowsStep, "TFLBM_ROWS3");
   s->ntiles3 = s->nstrips * ((ny + s->rows3 - 1) / s->rows3);
@@ -108,6 +120,10 @@ void plan_launches(tflbm_sim *s) {
   // g != 0 likewise 512^2 10.9 vs 12.9, 768^2 13.7 vs 15.1).
   const int64_t one_row_tiles = s->p.prec == kF16S ? 24LL * cus : (int64_t)occ1 * cus;
   s->fuse_fits = (int64_t)s->nstrips * ny > one_row_tiles;
+  // Three steps per pass: with the omega = 1 stages, on lattices with long
+  // enough chunks (kFuse3MinRowsPerSlot).
+  s->fuse3_fits = s->w1 && max_steps_per_pass(s->p.prec, s->w1) >= 3 && s->fuse_fits &&
+                  (int64_t)s->nstrips * ny >= kFuse3MinRowsPerSlot * (int64_t)occ3 * cus;
   // Reverse steps: at most two resident wavefronts per SIMD are planned for
   // (eight per CU).  At 4096^2 FP32 the one-step kernel, which fits three,
   // ran 9% faster with chunks sized for two than for three.
@@ -250,6 +266,11 @@ int tflbm_create(const tflbm_params *p, tflbm_sim **out) {
   tflbm_sim *s = new (std::nothrow) tflbm_sim();
   if (!s) return TFLBM_EINVAL;
   s->p = *p;
+  // omega = 1 exactly: the collision replaces the populations by the
+  // equilibrium, and the stages need no population history (TFLBM_OMEGA1=0
+  // keeps the general stages, which give the same bits)
+  s->w1 = p->tau == 1.0;
+  if (const char *e = std::getenv("TFLBM_OMEGA1")) s->w1 = s->w1 && std::atoi(e) != 0;
   s->ldx = (p->nx + 63) / 64 * 64;
   s->plane = (int64_t)p->ny * s->ldx;
   const size_t P = (size_t)s->plane;
@@ -331,16 +352,23 @@ int tflbm_init_fields(tflbm_sim *sim, const double *d_h0, const double *d_theta,
 // Launches nsteps steps kernel by kernel: passes of the most fused steps the
 // handle allows while that many remain, then shorter ones (with capture: the
 // moments of steps i .. i + ns - 1 of a pass, one capture block apart).
+// Most steps one launch of tflbm_step fuses on this handle.
+static int steps_per_pass(const tflbm_sim *sim) {
+  int ns = sim->fuse != 0 ? sim->fuse : (sim->fuse3_fits ? 3 : (sim->fuse_fits ? 2 : 1));
+  const int nsmax = max_steps_per_pass(sim->p.prec, sim->w1);
+  return ns > nsmax ? nsmax : ns;
+}
+
 static int launch_steps(tflbm_sim *sim, int64_t nsteps, void *d_capture, hipStream_t st) {
   const size_t cap_bytes = tflbm_capture_bytes(sim);
-  int ns_max = sim->fuse != 0 ? sim->fuse : (sim->fuse_fits ? 2 : 1);
-  if (ns_max > max_steps_per_pass(sim->p.prec)) ns_max = max_steps_per_pass(sim->p.prec);
+  int ns_max = steps_per_pass(sim);
+  if (d_capture && ns_max > 2) ns_max = 2;  // captures run at most two steps per pass
   int64_t i = 0;
   while (i < nsteps) {
     const int ns = (int)(nsteps - i < ns_max ? nsteps - i : ns_max);
     StepArgs A = make_step_args(sim, ns);
     A.capture = d_capture ? (char *)d_capture + (size_t)i * cap_bytes : nullptr;
-    const int rc = hip_status(sim, launch_step(sim->p.prec, ns, A, sim->kfield, d_capture != nullptr, st));
+    const int rc = hip_status(sim, launch_step(sim->p.prec, ns, A, sim->kfield, d_capture != nullptr, sim->w1, st));
     if (rc) return rc;
     sim->cur ^= 1;
     sim->steps += ns;
@@ -419,6 +447,12 @@ int tflbm_step_capture(tflbm_sim *sim, int64_t nsteps, void *d_capture, tflbm_st
 }
 
 int64_t tflbm_step_count(const tflbm_sim *sim) { return sim ? sim->steps : -1; }
+
+int tflbm_steps_per_pass(const tflbm_sim *sim) {
+  if (!sim) return TFLBM_EINVAL;
+  if (!sim->initialised) return TFLBM_ESTATE;
+  return steps_per_pass(sim);
+}
 
 int tflbm_step_graphs(const tflbm_sim *sim) {
   return sim ? (sim->gexec[0] != nullptr) + (sim->gexec[1] != nullptr) : -1;

@@ -32,7 +32,10 @@ constexpr double kCs2 = 1.0 / 3.0;
 //        HX = (64 V - B)/2 halo columns per side; NS fused steps consume
 //        3 NS of them (the stencil reaches 3 columns per step).  With V = 2
 //        HX is even, so that every lane's column pair is 8-byte aligned.
-//  NSMAX: the most fused steps per pass the halo allows.
+//  NSMAX: the most fused steps per pass the halo allows (three only with the
+//        omega = 1 stage, whose history lives in registers; the general
+//        stage keeps two rows of nine populations per step in LDS, and three
+//        of those cap a CU at five wavefronts).
 //  RB  : bytes per record.
 //  Each c_ly group of segments is padded to whole 128-byte lines and the
 //  step writes the padding too, so every line of a full record is written
@@ -40,30 +43,33 @@ constexpr double kCs2 = 1.0 / 3.0;
 constexpr int lines128(int bytes) { return (bytes + 127) / 128 * 128; }
 template <int P> struct Form;
 template <> struct Form<kF64> {
-  // segments of 416 B; groups of three padded from 1248 to 1280 B (10 lines);
-  // 30 lines per record.  Six halo columns: at most two fused steps (a third
-  // step, with a narrower record, measured no faster: its five wavefronts per
-  // CU leave the FP64 stages latency-bound)
+  // segments of 368 B; groups of three padded from 1104 to 1152 B (9 lines);
+  // 27 lines per record, an odd stride over the HBM channels.  Nine halo
+  // columns: three fused steps.  (52-site records with six halo columns, the
+  // most two steps need, ran two steps per pass 5 % faster, 58.0k against
+  // 54.9k MLUPS at 4096^2; three omega = 1 steps on 46-site records run at
+  // 70k.)
   using T = double;
-  static constexpr int V = 1, B = 52, SEG = B * 8, GRP = lines128(3 * SEG), RB = 3 * GRP, NSMAX = 2;
+  static constexpr int V = 1, B = 46, SEG = B * 8, GRP = lines128(3 * SEG), RB = 3 * GRP, NSMAX = 3;
 };
 template <> struct Form<kF32> {
-  // segments of 464 B; groups of three padded from 1392 to 1408 B (11 lines);
-  // 33 lines per record, an odd stride over the HBM channels.  Six halo
-  // columns: at most two fused steps (three, with 108-site records and ten
-  // halo columns, measured slower: 112.5k against 114k MLUPS at 4096^2; their
-  // 27.6 KB of LDS per wavefront leave five wavefronts per CU)
+  // segments of 432 B; groups of three padded from 1296 to 1408 B (11 lines);
+  // 33 lines per record, an odd stride over the HBM channels.  Ten halo
+  // columns (nine for three steps, rounded up to keep every lane's column
+  // pair 8-byte aligned): three fused steps.  Two steps per pass run as fast
+  // as on 116-site records (115k MLUPS at 4096^2).
   using T = float;
-  static constexpr int V = 2, B = 116, SEG = B * 4, GRP = lines128(3 * SEG), RB = 3 * GRP, NSMAX = 2;
+  static constexpr int V = 2, B = 108, SEG = B * 4, GRP = lines128(3 * SEG), RB = 3 * GRP, NSMAX = 3;
 };
 template <> struct Form<kF16S> {
   // source height deviation FP32 (464 B) and 8 FP16 segments of 232 B; the
   // c_ly groups start on lines: {s, slots 1-2} at 0 (1024 B), slots 3-5 at G1
   // (768 B), slots 6-8 at G2 (768 B), plus one unused line: 21 lines, an odd
   // stride (a power-of-two record stride puts the same segment of every
-  // record on the same few HBM channels).  At most two fused steps (three:
-  // 97k against 143k MLUPS at 4096^2, the VALU-bound stages starved at five
-  // wavefronts per CU)
+  // record on the same few HBM channels).  At most two fused steps: FP16S
+  // is bound by its VALU, which a third step (narrower records, more halo
+  // work per output) does not relieve (three with the LDS history: 97k
+  // against 143k MLUPS at 4096^2)
   using T = float;
   static constexpr int V = 2, B = 116, SEG = B * 2, NSMAX = 2;
   static constexpr int G1 = lines128(4 * B + 2 * SEG), G2 = G1 + lines128(3 * SEG);

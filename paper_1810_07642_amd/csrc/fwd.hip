@@ -250,7 +250,12 @@ __device__ __forceinline__ void shift_x(int l, const T *in, T *out) {
 // has zero momentum and is a fixed point of the collision at rest, so the
 // step on d is the step on f; only small changes of a film near href keep
 // more significant digits.
-template <int P, int KF> struct Stage {
+// W1 (omega = 1, tau = 1): BGK replaces the populations by the equilibrium,
+// so the emitted row needs only its moments: j is formed at ingest and waits
+// two rows in an LDS slot of two values per column (instead of nine), and
+// no populations are kept.  The values are those of the general stage bit
+// for bit: with 1 - omega = 0 its term (1 - omega) d adds an exact zero.
+template <int P, int KF, bool W1 = false> struct Stage {
   using T = typename Form<P>::T;
   static constexpr int V = Form<P>::V;
   T h0[V + 2], h1[V + 2], h2[V + 2];  // dh of rows r, r-1, r-2 with the left/right neighbours
@@ -260,7 +265,9 @@ template <int P, int KF> struct Stage {
   T sm1[V], sm2[V], sm3[V];
   T kn[V], kr[V];                     // kappa (or -gamma kappa) of rows r and r-1
   T an[V], ar[V];                     // -gamma/6 of rows r and r-1 (kGammaKappa)
-  T (*hist)[9][64 * V];
+  T jx2[V], jy2[V];                   // W1: j of row r-2, from ingest to finish
+  T (*hist)[9][64 * V];               // general: populations of rows r-1, r-2 [slot][l][column]
+  T (*jhist)[2][64 * V];              // W1: j of rows r-1, r-2 [slot][x or y][column]
 
   // kap, aco: the field values of row r (loaded with the row, load_kappa;
   // unused without a field)
@@ -285,18 +292,38 @@ template <int P, int KF> struct Stage {
         an[v] = aco[v];
       }
     }
-    // row r-2 leaves the LDS slot that row r takes over
-    const int slot = k & 1;
-    if (k >= 4) {
+    if constexpr (W1) {
+      // j = sum_l c_l d_l through the differences of opposite populations;
+      // row r-2's leaves the slot that row r's takes over
+      const int slot = k & 1;
+      if (k >= 4) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          jx2[v] = jhist[slot][0][V * lane + v];
+          jy2[v] = jhist[slot][1][V * lane + v];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const T d15 = f[1][v] - f[5][v], d37 = f[3][v] - f[7][v];
+        const T d26 = f[2][v] - f[6][v], d84 = f[8][v] - f[4][v];
+        jhist[slot][0][V * lane + v] = (d15 + d26) + d84;
+        jhist[slot][1][V * lane + v] = (d37 + d26) - d84;
+      }
+    } else {
+      // row r-2 leaves the LDS slot that row r takes over
+      const int slot = k & 1;
+      if (k >= 4) {
+#pragma unroll
+        for (int l = 0; l < 9; ++l)
+#pragma unroll
+          for (int v = 0; v < V; ++v) f2[l][v] = hist[slot][l][V * lane + v];
+      }
 #pragma unroll
       for (int l = 0; l < 9; ++l)
 #pragma unroll
-        for (int v = 0; v < V; ++v) f2[l][v] = hist[slot][l][V * lane + v];
+        for (int v = 0; v < V; ++v) hist[slot][l][V * lane + v] = f[l][v];
     }
-#pragma unroll
-    for (int l = 0; l < 9; ++l)
-#pragma unroll
-      for (int v = 0; v < V; ++v) hist[slot][l][V * lane + v] = f[l][v];
   }
 
   __device__ __forceinline__ bool finish(int k, const T (&f2)[9][V], T (&post)[9][V], T (&hv)[V], T (&jxv)[V],
@@ -345,11 +372,17 @@ template <int P, int KF> struct Stage {
 
         const T dh = h2[1 + v];
         const T h = C.href + dh;
-        // j = sum_l c_l d_l through the differences of opposite populations
-        const T d15 = f2[1][v] - f2[5][v], d37 = f2[3][v] - f2[7][v];
-        const T d26 = f2[2][v] - f2[6][v], d84 = f2[8][v] - f2[4][v];
-        const T jx = (d15 + d26) + d84;
-        const T jy = (d37 + d26) - d84;
+        T jx, jy;
+        if constexpr (W1) {
+          jx = jx2[v];
+          jy = jy2[v];
+        } else {
+          // j = sum_l c_l d_l through the differences of opposite populations
+          const T d15 = f2[1][v] - f2[5][v], d37 = f2[3][v] - f2[7][v];
+          const T d26 = f2[2][v] - f2[6][v], d84 = f2[8][v] - f2[4][v];
+          jx = (d15 + d26) + d84;
+          jy = (d37 + d26) - d84;
+        }
         const T inv_h = recip(h);
         const T ux = jx * inv_h, uy = jy * inv_h;
 
@@ -373,15 +406,22 @@ template <int P, int KF> struct Stage {
         const T usq = madd(ux, ux, uy * uy);
         const T hom = h * C.omega;
         const T G = C.omega * (C.g * dh * (h + C.href));  // omega q
-        post[0][v] = madd(C.om1, f2[0][v], madd(hom, usq * T(-2.0 / 3.0), madd(G, T(-5.0 / 6.0), C.omega * dh)));
+        const T e0 = madd(hom, usq * T(-2.0 / 3.0), madd(G, T(-5.0 / 6.0), C.omega * dh));
+        if constexpr (W1) post[0][v] = e0;
+        else post[0][v] = madd(C.om1, f2[0][v], e0);
         const T evA = madd(hom, usq * T(-1.0 / 6.0), G * T(1.0 / 6.0));    // E without (c.u)^2, axes
         const T evD = madd(hom, usq * T(-1.0 / 24.0), G * T(1.0 / 24.0));  // and diagonals
         auto opposite = [&](int lp, int lm, T cu, T cF, T ev, T w1, T w2) {
           const T hc = hom * cu;
           const T E = madd(hc, cu * w2, ev);
           const T O = hc + cF;
-          post[lp][v] = madd(O, w1, madd(C.om1, f2[lp][v], E));
-          post[lm][v] = madd(-O, w1, madd(C.om1, f2[lm][v], E));
+          if constexpr (W1) {
+            post[lp][v] = madd(O, w1, E);
+            post[lm][v] = madd(-O, w1, E);
+          } else {
+            post[lp][v] = madd(O, w1, madd(C.om1, f2[lp][v], E));
+            post[lm][v] = madd(-O, w1, madd(C.om1, f2[lm][v], E));
+          }
         };
         opposite(1, 5, ux, Fx, evA, T(1.0 / 3.0), T(0.5));
         opposite(3, 7, uy, Fy, evA, T(1.0 / 3.0), T(0.5));
@@ -398,6 +438,7 @@ template <int P, int KF> struct Stage {
       h2[v] = h1[v];
       h1[v] = h0[v];
     }
+
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       dx3[v] = dx2[v];
@@ -690,7 +731,9 @@ template <typename T, int V> struct Handoff {
 // A.capture, step t + s s capture blocks later.
 // G0 (FP16S only): the launch has g = 0, so the rest equilibrium of the
 // FP16S shift has no moving part and its code is left out.
-template <int P, int KF, bool CAP, int NS, bool G0 = false>
+// W1: omega = 1, the stages keep no populations (Stage) and the kernel no
+// LDS, which lets three fused steps keep eight wavefronts per CU.
+template <int P, int KF, bool CAP, int NS, bool G0 = false, bool W1 = false>
 __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   using T = typename Form<P>::T;
   constexpr int V = Form<P>::V;
@@ -699,7 +742,9 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   constexpr int HX = (64 * V - B) / 2;  // halo columns per side (>= 3 NS)
   constexpr int ES = sizeof(T);
   static_assert(HX >= 3 * NS, "halo columns too narrow for the fused steps");
-  __shared__ T hist[NS][2][9][64 * V];
+  // the stages' history of two rows: populations (general) or j (W1)
+  __shared__ T hist[W1 ? 1 : NS][W1 ? 1 : 2][W1 ? 1 : 9][W1 ? 1 : 64 * V];
+  __shared__ T jhist[W1 ? NS : 1][W1 ? 2 : 1][2][W1 ? 64 * V : 1];
 
   // XCD-aware tile order: consecutive workgroups land on different XCDs
   // (round robin), so give each XCD a contiguous block of tiles.
@@ -740,10 +785,16 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   L.fast_store = __all(L.pair || (!L.out[0] && !L.out[V - 1]));
   const Coef<T> C(A);
 
-  Stage<P, KF> S0, S1, S2;
-  S0.hist = hist[0];
-  if constexpr (NS >= 2) S1.hist = hist[1];
-  if constexpr (NS >= 3) S2.hist = hist[2];
+  Stage<P, KF, W1> S0, S1, S2;
+  if constexpr (W1) {
+    S0.jhist = jhist[0];
+    if constexpr (NS >= 2) S1.jhist = jhist[1];
+    if constexpr (NS >= 3) S2.jhist = jhist[2];
+  } else {
+    S0.hist = hist[0];
+    if constexpr (NS >= 2) S1.hist = hist[1];
+    if constexpr (NS >= 3) S2.hist = hist[2];
+  }
   Handoff<T, V> H1, H2;  // stage 0 -> 1, stage 1 -> 2
   int bad = 0;
   const size_t capblk = (size_t)ny * A.nblk * cap_record_bytes<P>();
@@ -755,7 +806,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   // rows are loaded PF rows ahead of their use.  Measured at 4096^2 (MLUPS,
   // two rows ahead / three): FP16S 142.8k / 146.9k (its decoding makes each
   // row wait longer for its loads), FP32 113.9k / 113.3k, FP64 57.9k / 58.0k.
-  constexpr int PF = P == kF16S ? 3 : 2;
+  constexpr int PF = P == kF16S ? 3 : (NS == 3 ? 1 : 2);
   int rpre = (ry + PF) % ny;                             // row r + PF
   // FP16S decodes row r with rows r - 1 and r + 1 (fp16s_decode): the row
   // above the first is read for its s and q_6..q_8, and one row past the
@@ -792,7 +843,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   };
   load_buf(rsrc_src(ry), fa);
   if constexpr (KF != kNoField) load_kappa<P, KF>(rsrc_kap(ry), L, ka);
-  if (KL > 1) {
+  if (PF >= 2 && KL > 1) {
     const int r1 = (ry + 1) % ny;
     load_buf(rsrc_src(r1), fb);
     if constexpr (KF != kNoField) load_kappa<P, KF>(rsrc_kap(r1), L, kb);
@@ -915,12 +966,14 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
     }
     if (k < K) iteration(k, fa, fb, ka);
     if (k + 1 < K) iteration(k + 1, fb, fc, kb);
-  } else {
+  } else if constexpr (PF == 2) {
     for (; k + 1 < K; k += 2) {
       iteration(k, fa, fb, ka);
       iteration(k + 1, fb, fa, kb);
     }
     if (k < K) iteration(k, fa, fb, ka);
+  } else {
+    for (; k < K; ++k) iteration(k, fa, fa, ka);
   }
 
   const unsigned long long m = __ballot(bad);
@@ -1091,81 +1144,88 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s) 
 }
 
 // ---- launchers -----------------------------------------------------------------
-template <int P, int NS, bool G0, int KF>
+template <int P, int NS, bool G0, int KF, bool W1>
 static void launch_step_k(const StepArgs &A, bool cap, hipStream_t s) {
   const dim3 grid(8 * A.per_xcd), block(64);
-  if (cap) step_kernel<P, KF, true, NS, G0><<<grid, block, 0, s>>>(A);
-  else step_kernel<P, KF, false, NS, G0><<<grid, block, 0, s>>>(A);
+  if constexpr (NS <= 2) {  // captures run at most two steps per pass
+    if (cap) {
+      step_kernel<P, KF, true, NS, G0, W1><<<grid, block, 0, s>>>(A);
+      return;
+    }
+  }
+  step_kernel<P, KF, false, NS, G0, W1><<<grid, block, 0, s>>>(A);
 }
 
-template <int P, int NS, bool G0>
+template <int P, int NS, bool G0, bool W1>
 static void launch_step_v(const StepArgs &A, int kf, bool cap, hipStream_t s) {
-  if (kf == kGammaKappa) launch_step_k<P, NS, G0, kGammaKappa>(A, cap, s);
-  else if (kf == kKappa) launch_step_k<P, NS, G0, kKappa>(A, cap, s);
-  else launch_step_k<P, NS, G0, kNoField>(A, cap, s);
+  if (kf == kGammaKappa) launch_step_k<P, NS, G0, kGammaKappa, W1>(A, cap, s);
+  else if (kf == kKappa) launch_step_k<P, NS, G0, kKappa, W1>(A, cap, s);
+  else launch_step_k<P, NS, G0, kNoField, W1>(A, cap, s);
 }
 
-template <int P, int NS>
+template <int P, int NS, bool W1>
 static hipError_t launch_step_p(const StepArgs &A, int kf, bool cap, hipStream_t s) {
   if constexpr (P == kF16S) {
     if (A.g == 0.0) {
-      launch_step_v<P, NS, true>(A, kf, cap, s);
+      launch_step_v<P, NS, true, W1>(A, kf, cap, s);
       return hipGetLastError();
     }
   }
-  launch_step_v<P, NS, false>(A, kf, cap, s);
+  launch_step_v<P, NS, false, W1>(A, kf, cap, s);
   return hipGetLastError();
 }
 
-template <int P>
+template <int P, bool W1>
 static hipError_t launch_step_ns(int ns, const StepArgs &A, int kf, bool cap, hipStream_t s) {
   if constexpr (Form<P>::NSMAX >= 3) {
-    if (ns == 3) return launch_step_p<P, 3>(A, kf, cap, s);
+    if (ns == 3) return launch_step_p<P, 3, W1>(A, kf, cap, s);
   }
-  if (ns > Form<P>::NSMAX) return hipErrorInvalidValue;
-  if (ns == 2) return launch_step_p<P, 2>(A, kf, cap, s);
-  return launch_step_p<P, 1>(A, kf, cap, s);
+  if (ns > 2) return hipErrorInvalidValue;
+  if (ns == 2) return launch_step_p<P, 2, W1>(A, kf, cap, s);
+  return launch_step_p<P, 1, W1>(A, kf, cap, s);
 }
 
-hipError_t launch_step(int prec, int ns, const StepArgs &A, int kf, bool cap, hipStream_t s) {
+hipError_t launch_step(int prec, int ns, const StepArgs &A, int kf, bool cap, bool w1, hipStream_t s) {
+  if (ns < 1 || ns > max_steps_per_pass(prec, w1) || (cap && ns > 2)) return hipErrorInvalidValue;
   switch (prec) {
-    case kF64: return launch_step_ns<kF64>(ns, A, kf, cap, s);
-    case kF32: return launch_step_ns<kF32>(ns, A, kf, cap, s);
-    default: return launch_step_ns<kF16S>(ns, A, kf, cap, s);
+    case kF64: return w1 ? launch_step_ns<kF64, true>(ns, A, kf, cap, s) : launch_step_ns<kF64, false>(ns, A, kf, cap, s);
+    case kF32: return w1 ? launch_step_ns<kF32, true>(ns, A, kf, cap, s) : launch_step_ns<kF32, false>(ns, A, kf, cap, s);
+    default: return w1 ? launch_step_ns<kF16S, true>(ns, A, kf, cap, s) : launch_step_ns<kF16S, false>(ns, A, kf, cap, s);
   }
 }
 
-template <int P, int NS, bool G0>
+template <int P, int NS, bool G0, bool W1>
 static int occupancy_v(int kf) {
   int n = 0;
   const hipError_t e =
-      kf == kGammaKappa ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, kGammaKappa, false, NS, G0>, 64, 0)
-      : kf == kKappa    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, kKappa, false, NS, G0>, 64, 0)
-                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, kNoField, false, NS, G0>, 64, 0);
+      kf == kGammaKappa
+          ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, kGammaKappa, false, NS, G0, W1>, 64, 0)
+      : kf == kKappa ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, kKappa, false, NS, G0, W1>, 64, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<P, kNoField, false, NS, G0, W1>, 64, 0);
   return e == hipSuccess ? n : 0;
 }
 
-template <int P>
+template <int P, bool W1>
 static int occupancy_p(int kf, int ns, bool g0) {
   if constexpr (Form<P>::NSMAX >= 3) {
-    if (ns == 3) return P == kF16S && g0 ? occupancy_v<P, 3, true>(kf) : occupancy_v<P, 3, false>(kf);
+    if (ns == 3) return occupancy_v<P, 3, false, W1>(kf);
   }
-  if (ns > Form<P>::NSMAX) return 0;
+  if (ns > 2) return 0;
   if constexpr (P == kF16S) {
-    if (g0) return ns == 2 ? occupancy_v<P, 2, true>(kf) : occupancy_v<P, 1, true>(kf);
+    if (g0) return ns == 2 ? occupancy_v<P, 2, true, W1>(kf) : occupancy_v<P, 1, true, W1>(kf);
   }
-  return ns == 2 ? occupancy_v<P, 2, false>(kf) : occupancy_v<P, 1, false>(kf);
+  return ns == 2 ? occupancy_v<P, 2, false, W1>(kf) : occupancy_v<P, 1, false, W1>(kf);
 }
 
-int max_steps_per_pass(int prec) {
+int max_steps_per_pass(int prec, bool) {
   return prec == kF64 ? Form<kF64>::NSMAX : (prec == kF32 ? Form<kF32>::NSMAX : Form<kF16S>::NSMAX);
 }
 
-int step_blocks_per_cu(int prec, int kf, int ns, bool g0) {
+int step_blocks_per_cu(int prec, int kf, int ns, bool g0, bool w1) {
   switch (prec) {
-    case kF64: return occupancy_p<kF64>(kf, ns, g0);
-    case kF32: return occupancy_p<kF32>(kf, ns, g0);
-    default: return occupancy_p<kF16S>(kf, ns, g0);
+    case kF64: return w1 ? occupancy_p<kF64, true>(kf, ns, g0) : occupancy_p<kF64, false>(kf, ns, g0);
+    case kF32: return w1 ? occupancy_p<kF32, true>(kf, ns, g0) : occupancy_p<kF32, false>(kf, ns, g0);
+    default: return w1 ? occupancy_p<kF16S, true>(kf, ns, g0) : occupancy_p<kF16S, false>(kf, ns, g0);
   }
 }
 

@@ -19,11 +19,14 @@ int record_bytes(int prec);
 // ns fused time steps in one pass (1, 2 or 3; src at time t, dst at time
 // t + ns).  kfield: the per-site field the step reads: 0 none, 1 kappa, 2 the
 // pairs (-gamma/6, -gamma kappa) of a position-dependent surface tension.
-hipError_t launch_step(int prec, int ns, const StepArgs &A, int kfield, bool capture, hipStream_t s);
-// Most fused steps per pass of a storage form (its halo columns allow 3 per step).
-int max_steps_per_pass(int prec);
+// w1: omega = 1 (tau = 1), the stages without a population history.
+// Captures run at most two steps per pass.
+hipError_t launch_step(int prec, int ns, const StepArgs &A, int kfield, bool capture, bool w1, hipStream_t s);
+// Most fused steps per pass of a storage form: its halo columns allow three
+// per step, and three need the omega = 1 stages.
+int max_steps_per_pass(int prec, bool w1);
 // Resident one-wavefront workgroups per CU of the step kernel (0 if unknown).
-int step_blocks_per_cu(int prec, int kfield, int ns, bool g0);
+int step_blocks_per_cu(int prec, int kfield, int ns, bool g0, bool w1);
 hipError_t launch_init(int prec, const StepArgs &A, const double *h0, const double *theta, const double *gamma,
                        int field, double kconst, hipStream_t s);
 hipError_t launch_read(int prec, const StepArgs &A, double *h, double *ux, double *uy, hipStream_t s);

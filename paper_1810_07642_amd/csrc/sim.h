@@ -26,8 +26,10 @@ struct tflbm_sim {
   int nstrips = 0, rows = 0, ntiles = 0, per_xcd = 0;
   int rows2 = 0, ntiles2 = 0, per_xcd2 = 0;
   int rows3 = 0, ntiles3 = 0, per_xcd3 = 0;
-  int fuse = 0;           // most steps per pass: 1, 2 or 3; 0 = 2 if fuse_fits, else 1
+  int fuse = 0;           // most steps per pass: 1, 2 or 3; 0 = by lattice size (fuse3_fits, fuse_fits)
   bool fuse_fits = false; // the lattice is too large for one round of one-row tiles
+  bool fuse3_fits = false;  // three steps per pass (omega = 1) beat two on this lattice
+  bool w1 = false;        // omega = 1 (tau = 1): the stages without a population history
   // launch-bound lattices: blocks of steps replayed from captured graphs, one
   // per starting buffer parity, captured on a stream of the library's own
   bool graphs = false;

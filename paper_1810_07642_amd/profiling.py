@@ -43,7 +43,13 @@ N4096 = 4096 * 4096
 # Algorithmic bytes per site of one pass of the fused two-step kernel: every
 # record read and written once (9 populations) plus the kappa field read once.
 STEP_BYTES = {"fp64": (80, 72), "fp32": (40, 36), "fp16s": (24, 20)}  # (read, write) per site
-STEP_KERNEL_PREC = {"fp64": 0, "fp32": 1, "fp16s": 2}
+# The kernel the benchmark workload (tau = 1, 4096^2) runs per form and the
+# steps one launch of it advances: three fused steps of the omega = 1 stages
+# in FP64 and FP32, two in FP16S (g = 0).
+STEP_KERNEL = {"fp64": ("step_kernel<0, 1, false, 3, false, true>", 3),
+               "fp32": ("step_kernel<1, 1, false, 3, false, true>", 3),
+               "fp16s": ("step_kernel<2, 1, false, 2, true, true>", 2)}
+PROFILE_STEPS = 24  # a multiple of 2 and of 3: whole passes of the kernel
 # The two-step reverse pass (FP32 adjoint): adjoint 36 + two captures 24 +
 # kappa 4 + g_kappa 8 read; adjoint 36 + g_kappa 8 written.
 ADJ_BYTES = (72, 44)
@@ -236,7 +242,7 @@ def trace_summary(trace_dir, command, title):
 
 
 def _step_cmds(storage):
-    base = f"python3 <repo>/bench.py --profile-steps 20 --profile-storage {storage}"
+    base = f"python3 <repo>/bench.py --profile-steps {PROFILE_STEPS} --profile-storage {storage}"
     return [f"rocprofv3 --pmc {c} --output-format csv -d <repo>/gpurun_out/step_{storage}_{c} -o run -- {base}"
             for c in ("FETCH_SIZE", "WRITE_SIZE")]
 
@@ -267,15 +273,16 @@ def main(argv=None):
         cmds = _step_cmds(args.storage)
         if args.sq_command:
             cmds.append(args.sq_command)
+        kname, spp = STEP_KERNEL[args.storage]
         text = traffic_summary(
             f"HBM traffic of the {args.storage.upper()} step kernel, patterned dewetting 4096 x 4096",
-            f"{args.storage.upper()} storage, kappa field, 2 time steps per launch",
-            rf"step_kernel<{STEP_KERNEL_PREC[args.storage]}, 1, false, 2,", args.fetch, args.write,
-            r * N4096, w * N4096, 2, STEP_SOURCES, cmds, sq_dir=args.sq, trace_dir=args.trace,
+            f"{args.storage.upper()} storage, kappa field, {spp} time steps per launch, omega = 1 stages",
+            re.escape(kname), args.fetch, args.write,
+            r * N4096, w * N4096, spp, STEP_SOURCES, cmds, sq_dir=args.sq, trace_dir=args.trace,
             alg_desc=f"records read and written once and the kappa field read once ({r}/{w} B/site)",
-            notes=["`bench.py --profile-steps 20` runs 20 steps (10 launches) of the benchmark workload, "
-                   "a record copy of one population buffer (tflbm_state_save) and a 1 GiB runtime copy "
-                   "that calibrates the counters."])
+            notes=[f"`bench.py --profile-steps {PROFILE_STEPS}` runs {PROFILE_STEPS} steps "
+                   f"({PROFILE_STEPS // spp} launches) of the benchmark workload, a record copy of one population "
+                   "buffer (tflbm_state_save) and a 1 GiB runtime copy that calibrates the counters."])
     else:
         cmds = [f"rocprofv3 --pmc {c} --output-format csv -d <repo>/gpurun_out/adj_{c} -o run -- "
                 f"python3 <repo>/bench.py --profile-adjoint 16" for c in ("FETCH_SIZE", "WRITE_SIZE")]

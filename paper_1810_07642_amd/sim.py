@@ -146,6 +146,14 @@ class Sim:
         return int(self.lib.tflbm_step_count(self.h))
 
     @property
+    def steps_per_pass(self):
+        """Most time steps one pass of tflbm_step advances on this handle."""
+        n = int(self.lib.tflbm_steps_per_pass(self.h))
+        if n < 0:
+            raise RuntimeError(f"tflbm_steps_per_pass: {n}")
+        return n
+
+    @property
     def step_graphs(self):
         """Step graphs the handle holds (tflbm_step replays blocks of steps
         from them on launch-bound lattices)."""

@@ -75,7 +75,7 @@ def test_friction_stability_warning(lib):
 
 
 # population records: (sites per record, bytes per record) of each storage form
-RECORDS = {0: (52, 3840), 1: (116, 4224), 2: (116, 2688)}
+RECORDS = {0: (46, 3456), 1: (108, 4224), 2: (116, 2688)}
 
 
 @pytest.mark.parametrize("prec,per_site", [(0, 72), (1, 36), (2, 20)])

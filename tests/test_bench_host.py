@@ -42,7 +42,7 @@ def test_committed_step_summaries_match_the_sources(form):
     val = bench.committed_traffic(form)
     assert val is not None, f"profiles for {form} are stale or missing"
     alg = bench.BYTES_PER_SITE[form] * 4096 * 4096
-    assert val[1] == 2 and alg <= val[0] <= 1.5 * alg
+    assert val[1] == profiling.STEP_KERNEL[form][1] and alg <= val[0] <= 1.5 * alg
 
 
 def test_committed_adjoint_summary_matches_the_sources():
@@ -59,7 +59,8 @@ def test_roofline_block_is_a_fraction_of_the_peak():
     assert abs(blk["frac"] - blk["achieved"] / 8000.0) < 1e-4
     assert abs(blk["traffic"] - 1.1 * blk["achieved"]) < 0.2
     assert abs(blk["ceiling"]["frac_of_ceiling"] - blk["achieved"] / 5000.0) < 1e-4
-    assert bench.launches(20) == 10 and bench.launches(21) == 11
+    assert bench.launches(20, 2) == 10 and bench.launches(21, 2) == 11
+    assert bench.launches(21, 3) == 7 and bench.launches(20, 3) == 7 and bench.launches(24, 3) == 8
 
 
 def test_more_than_one_gpu_is_refused():

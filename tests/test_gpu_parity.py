@@ -333,6 +333,44 @@ def test_fused_steps_equal_single_steps_bitwise(prec, href, g):
                 assert torch.equal(a, b), (prec, href, ny, nx)
 
 
+@pytest.mark.parametrize("g", [1e-3, 0.0])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+def test_omega1_stages_equal_general_stages_bitwise(prec, g):
+    """At tau = 1 the collision replaces the populations by the equilibrium
+    and the library runs stages that keep no populations (and, in FP64 and
+    FP32, three steps per pass).  Against the general stages (TFLBM_OMEGA1=0)
+    at one step per pass: the same bits for one, two and three steps per pass,
+    with a theta field, with uniform theta and with a surface tension field, on
+    ragged, odd and degenerate grids (7 steps end on a shorter pass); and the
+    same captures of the moments."""
+    import os
+    from paper_1810_07642_amd import Sim
+    from test_gpu_gamma import gamma_field
+    p = dict(tau=1.0, gamma=0.01, g=g, hstar=0.1, delta=1.0, ax=1e-5, ay=-1e-5)
+    for (ny, nx) in [(70, 150), (23, 37), (1, 1), (6, 300), (130, 97)]:
+        h0, th = random_case(ny, nx, 43)
+        for field in ("theta", "uniform", "gamma"):
+            banner(f"omega = 1 stages vs general: {prec} g={g} {ny}x{nx} {field}")
+            runs = []
+            for omega1, fuse in (("0", "1"), ("1", "1"), ("1", "2"), ("1", "3"), ("0", "2")):
+                os.environ["TFLBM_FUSE"] = fuse
+                os.environ["TFLBM_OMEGA1"] = omega1
+                try:
+                    sim = Sim(nx, ny, prec, gamma_field=field == "gamma", **p)
+                finally:
+                    del os.environ["TFLBM_FUSE"], os.environ["TFLBM_OMEGA1"]
+                sim.init(h0, None if field == "uniform" else th,
+                         gamma_field(ny, nx, 44) if field == "gamma" else None)
+                sim.step(7)
+                sim.check()
+                cap = torch.zeros(4 * sim.capture_bytes(), dtype=torch.uint8, device=sim.device)
+                sim.step_capture(4, cap)
+                runs.append((sim.state_save().cpu(), cap.cpu()) + tuple(t.cpu() for t in sim.read()))
+            for other in runs[1:]:
+                for a, b in zip(other, runs[0]):
+                    assert torch.equal(a, b), (prec, g, ny, nx, field)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
 def test_graph_replayed_steps_equal_launched_steps_bitwise(prec):
     """On launch-bound lattices tflbm_step sends whole blocks of 64 steps as
