@@ -37,9 +37,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
 # write each of the 9 populations once, plus the kappa field read once.
 BYTES_PER_SITE = {"fp64": 152, "fp32": 76, "fp16s": 44}
 HREF = {"fp64": 0.0, "fp32": 0.1, "fp16s": 0.1}  # storage reference height: the film's mean
-# Reverse pass, two steps per launch, FP32 adjoint with FP64 kappa gradient:
-# adjoint read and write 36 + 36, two captures 24, kappa 4, g_kappa RMW 16.
-ADJ2_BYTES_PER_SITE = 116
+# Reverse pass, two steps per launch, FP32 adjoint with FP64 kappa gradient,
+# at tau = 1 (the adjoint between steps as three fields per site): fields
+# read and written 12 + 12, two captures 24, kappa 4, g_kappa RMW 16.  (The
+# general pass moves nine adjoint populations each way: 116 B.)
+ADJ2_BYTES_PER_SITE = 68
 PROFILES = os.path.join(ROOT, "profiles")
 EXTRA_STEPS = 400   # timed steps of each form in the per-form table (independent of --steps)
 ACCURACY_STEPS = 2000  # fixed horizon of the accuracy legs
@@ -270,7 +272,7 @@ def reverse_sweep_at(n, ceiling_gbs, K=16):
     two steps per pass (tflbm_adj_steps, what the backward pass runs) and one
     step per pass (tflbm_adj_step); the backward/forward ratio they give
     (checkpoint copies excluded), and the roofline block of the two-step
-    reverse kernel (116 B per site and pass)."""
+    reverse kernel (68 B per site and pass at tau = 1)."""
     import ctypes
     import torch
     from paper_1810_07642_amd import Sim, inputs
@@ -307,7 +309,8 @@ def reverse_sweep_at(n, ceiling_gbs, K=16):
             "adjoint_us_per_step": round(a2 * 1e3, 1), "ratio": round((c + a2) / f, 3),
             "adjoint_one_step_per_pass_us_per_step": round(a1 * 1e3, 1),
             "ratio_one_step_per_pass": round((c + a1) / f, 3),
-            "roofline": roofline_block("adj_step2_kernel<float, kappa field> (two reverse steps per launch)",
+            "roofline": roofline_block("adj_step2_kernel<float, kappa field, three adjoint fields per site> "
+                                       "(two reverse steps per launch)",
                                        ADJ2_BYTES_PER_SITE * n * n, 2 * a2, committed_adj_traffic(), ceiling_gbs)}
 
 

@@ -126,9 +126,9 @@ int tflbm_check_params(const tflbm_params *p);
  * does not prevent creation.  *out receives the handle or NULL.
  * Launch-shape overrides, read from the environment here (fusion) and at
  * tflbm_init (row chunks), for measurement only; results do not depend on
- * them: TFLBM_FUSE=1, 2 or 3 (most forward steps per pass in tflbm_step;
- * tflbm_step_capture runs at most two; by default three with tau = 1 on
- * large lattices, else two where the lattice is large enough for it to pay),
+ * them: TFLBM_FUSE=1, 2 or 3 (most forward steps per pass in tflbm_step and
+ * tflbm_step_capture; by default three with tau = 1 on large lattices, else
+ * two where the lattice is large enough for it to pay),
  * TFLBM_OMEGA1=0 (with tau = 1, the general collision stages instead of the
  * ones that keep no populations; the same bits), TFLBM_ADJ_FUSE=1 or 2 (the
  * same for the reverse steps of tflbm_adj_steps; by default two where the

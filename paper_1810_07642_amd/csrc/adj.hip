@@ -53,8 +53,21 @@ template <typename T> struct AdjRec {
   __host__ __device__ static constexpr int seg(int l) { return kSlot[l] * SEG; }
 };
 
+// With omega = 1 the step's adjoint is lambda^t_l = lambda_h + c_l . lambda_j
+// (lam_of): three fields per site carry it between steps instead of nine
+// populations.  They are stored at the site itself in records of 64 slots per
+// field, [ny][nstrips][3][64] (lambda_h, lambda_jx, lambda_jy): the strip's
+// kAdjW columns in slots 0 .. kAdjW-1 and ten padding slots that the halo
+// lanes write, so a strip writes whole lines; the reverse step at (x, y)
+// forms mu_l(x, y) = lambda_l(x + c_l) from the fields at column x + c_lx of
+// row y + c_ly.
+template <typename T> struct AdjRec1 {
+  static constexpr int SEG = 64 * (int)sizeof(T);
+  static constexpr int RB = 3 * SEG;
+};
+
 struct AdjArgs {
-  const char *src;     // adjoint records at the end of step t (AdjRec)
+  const char *src;     // adjoint records at the end of step t (AdjRec; AdjRec1 with omega = 1)
   char *dst;           // adjoint records at the end of step t-1
   const char *cap;     // h, jx, jy of step t: capture records of the forward form
   const char *cap2;    // the same for step t-1 (two-step pass only)
@@ -108,6 +121,8 @@ template <typename T> struct AdjCoef {
 template <typename T> struct AdjLane {
   int nu[3];  // adjoint entry of columns a - 1, a, a + 1 (by c_lx + 1)
   int st;     // the lane's entry in its strip's record; kDropOffset for the halo lanes
+  int nu1[3];  // omega = 1: field entry of columns a - 1, a, a + 1 (AdjRec1)
+  int st1;     // omega = 1: the lane's slot in its strip's record (the halo lanes: padding)
   int cap;    // capture entry of column a
   int kap;    // kappa entry of column a
   int gk;     // dLoss/dkappa entry (the halo lanes: the record's padding)
@@ -121,8 +136,15 @@ template <typename T> struct AdjLane {
       const int s = col / kAdjW;
       nu[c] = s * AdjRec<T>::RB + (col - s * kAdjW) * (int)sizeof(T);
     }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int col = wrap(a + c - 1, A.nx);
+      const int s = col / kAdjW;
+      nu1[c] = s * AdjRec1<T>::RB + (col - s * kAdjW) * (int)sizeof(T);
+    }
     out = a >= x0 && a < xend;
     st = out ? strip * AdjRec<T>::RB + (a - x0) * (int)sizeof(T) : kDropOffset;
+    st1 = strip * AdjRec1<T>::RB + ((lane - kAdjHalo) & 63) * (int)sizeof(T);
     const int col = wrap(a, A.nx);
     const int cb = col / A.capB;
     cap = cb * A.capRB + (col - cb * A.capB) * (int)sizeof(T);
@@ -130,6 +152,16 @@ template <typename T> struct AdjLane {
     gk = strip * kGkRB + ((lane - kAdjHalo) & 63) * 8;
   }
 };
+
+// lambda_l = lambda_h + c_l . lambda_j: the part of the step's adjoint that
+// does not depend on mu (the whole of it when omega = 1).
+template <typename T> __device__ __forceinline__ T lam_of(int l, T lh, T ljx, T ljy) {
+  const int cx = kCx[l], cy = kCy[l];
+  const T cl = cx == 0 ? (cy == 0 ? T(0) : (cy > 0 ? ljy : -ljy))
+                       : (cy == 0 ? (cx > 0 ? ljx : -ljx)
+                                  : (cx > 0 ? (cy > 0 ? ljx + ljy : ljx - ljy) : (cy > 0 ? ljy - ljx : -ljx - ljy)));
+  return lh + cl;
+}
 
 // One input row of a reverse stage: the adjoint read (mu) and the forward
 // moments and kappa of the same row.
@@ -158,6 +190,61 @@ __device__ __forceinline__ void load_mu(const AdjArgs &A, const AdjLane<T> &L, i
   const rsrc_t r = make_rsrc(A.src + (size_t)row * rb, rb);
 #pragma unroll
   for (int l = 0; l < 9; ++l) mu[l] = ld_t<T>(r, L.nu[kCx[l] + 1] + AdjRec<T>::seg(l));
+}
+
+// omega = 1: lambda_h, lambda_jx, lambda_jy of a row at the columns x - 1,
+// x, x + 1, as v[3 f + c] (f: the field, c = c_lx + 1).
+template <typename T>
+__device__ __forceinline__ void load_fields(const AdjArgs &A, const AdjLane<T> &L, int row, T (&v)[9]) {
+  const uint32_t rb = (uint32_t)A.nstrips * AdjRec1<T>::RB;
+  const rsrc_t r = make_rsrc(A.src + (size_t)row * rb, rb);
+#pragma unroll
+  for (int f = 0; f < 3; ++f)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[3 * f + c] = ld_t<T>(r, L.nu1[c] + f * AdjRec1<T>::SEG);
+}
+
+// omega = 1: mu of consecutive rows from the fields of the rows around them.
+// The fields of row q give mu_l of row q - c_ly for every l; feeding row q
+// completes mu of row q - 1 (its c_ly = +1 values come last) and leaves the
+// parts of rows q and q + 1.
+template <typename T> struct MuFromFields {
+  T mc[3] = {0, 0, 0};  // mu_6, mu_7, mu_8 (c_ly = -1) of row q, from row q - 1
+  T zc[3] = {0, 0, 0};  // mu_0, mu_1, mu_5 (c_ly = 0) of row q
+  T mn[3] = {0, 0, 0};  // mu_6, mu_7, mu_8 of row q + 1, from row q
+  __device__ __forceinline__ void feed(const T (&v)[9], T (&mu)[9]) {
+    auto at = [&](int l) {
+      const int c = kCx[l] + 1;
+      return lam_of(l, v[c], v[3 + c], v[6 + c]);
+    };
+    mu[2] = at(2);
+    mu[3] = at(3);
+    mu[4] = at(4);
+    mu[0] = zc[0];
+    mu[1] = zc[1];
+    mu[5] = zc[2];
+    mu[6] = mc[0];
+    mu[7] = mc[1];
+    mu[8] = mc[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) mc[i] = mn[i];
+    zc[0] = at(0);
+    zc[1] = at(1);
+    zc[2] = at(5);
+    mn[0] = at(6);
+    mn[1] = at(7);
+    mn[2] = at(8);
+  }
+};
+
+// omega = 1: stores lambda_h, lambda_j of row y at the lane's slot.
+template <typename T>
+__device__ __forceinline__ void store_fields(const AdjArgs &A, const AdjLane<T> &L, int y, T lh, T ljx, T ljy) {
+  const uint32_t rb = (uint32_t)A.nstrips * AdjRec1<T>::RB;
+  const rsrc_t r = make_rsrc(A.dst + (size_t)y * rb, rb);
+  st_t(r, L.st1, lh);
+  st_t(r, L.st1 + AdjRec1<T>::SEG, ljx);
+  st_t(r, L.st1 + 2 * AdjRec1<T>::SEG, ljy);
 }
 
 // h, j_x, j_y of a row from the capture records of a forward step.
@@ -240,6 +327,16 @@ template <typename T> struct AdjStage {
   // Adjoint populations lambda^t_l of row r-2 from that row's mu, and the
   // row's term -gamma phi(h) lambda_p of dLoss/dkappa.
   __device__ __forceinline__ void out(const T (&mu)[9], T (&lam)[9], double &gterm, const AdjCoef<T> &C) const {
+    T lh, ljx, ljy;
+    out_moments(mu, lh, ljx, ljy, gterm, C);
+#pragma unroll
+    for (int l = 0; l < 9; ++l) lam[l] = madd(C.om1, mu[l], lam_of(l, lh, ljx, ljy));
+  }
+
+  // lambda_h and lambda_j of row r-2 (lambda^t_l = (1 - omega) mu_l +
+  // lambda_h + c_l . lambda_j), and the row's term of dLoss/dkappa.
+  __device__ __forceinline__ void out_moments(const T (&mu)[9], T &lh_out, T &ljx_out, T &ljy_out, double &gterm,
+                                              const AdjCoef<T> &C) const {
     const T h = h2, inv_h = ih2;
     const T ux = jx2 * inv_h, uy = jy2 * inv_h;
     // forward pressure gradient (p rows r-3 .. r-1)
@@ -294,15 +391,9 @@ template <typename T> struct AdjStage {
     T lh = C.omega * sh + Fx2 * (-Gx - C.nu * dalpha * ux + C.ax) + Fy2 * (-Gy - C.nu * dalpha * uy + C.ay) -
            C.gamma * lapq - C.gamma * k2 * dphi * lp;
     lh -= (lux * ux + luy * uy) * inv_h;
-    const T ljx = lux * inv_h, ljy = luy * inv_h;
-#pragma unroll
-    for (int l = 0; l < 9; ++l) {
-      const int cx = kCx[l], cy = kCy[l];
-      const T cl = cx == 0 ? (cy == 0 ? T(0) : (cy > 0 ? ljy : -ljy))
-                           : (cy == 0 ? (cx > 0 ? ljx : -ljx)
-                                      : (cx > 0 ? (cy > 0 ? ljx + ljy : ljx - ljy) : (cy > 0 ? ljy - ljx : -ljx - ljy)));
-      lam[l] = madd(C.om1, mu[l], lh + cl);
-    }
+    lh_out = lh;
+    ljx_out = lux * inv_h;
+    ljy_out = luy * inv_h;
     gterm = -(double)C.gamma * (double)phi * (double)lp;
   }
 };
@@ -326,8 +417,8 @@ __device__ __forceinline__ void store_lambda(const AdjArgs &A, const AdjLane<T> 
 // One reverse step.  A workgroup is one wavefront marching up a strip of
 // kAdjW columns (plus kAdjHalo halo columns per side, of which the stencils
 // of one step need two) over a chunk of rows; it reads rows y0-2 .. yend+1
-// and writes rows y0 .. yend-1.
-template <typename T, bool KF>
+// (W1: the fields of rows y0-3 .. yend+2) and writes rows y0 .. yend-1.
+template <typename T, bool KF, bool W1 = false>
 __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
   const int b = blockIdx.x;
   const int tile = (b & 7) * A.per_xcd + (b >> 3);
@@ -348,18 +439,33 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
 
   const int K = (yend - y0) + 4;
   int ry = wrap(y0 - 2, ny);
+  // W1: mu of row r needs the fields of rows r-1 .. r+1; they are read one
+  // row ahead and fed into `mf`, which completes mu of the row before
+  MuFromFields<T> mf;
   auto load_row = [&](int row) {
-    load_mu(A, L, row, mun);
+    if constexpr (W1) load_fields(A, L, row + 1 == ny ? 0 : row + 1, mun);
+    else load_mu(A, L, row, mun);
     load_cap(A, A.cap, L, row, hn, jxn, jyn);
     if constexpr (KF) kn = load_kap(A, L, row);
   };
+  if constexpr (W1) {
+    T v[9], unused[9];
+    load_fields(A, L, wrap(y0 - 3, ny), v);
+    mf.feed(v, unused);
+    load_fields(A, L, ry, v);
+    mf.feed(v, unused);
+  }
   load_row(ry);
   double gkn = ld_f64(gk_row(A, y0), L.gk);  // dLoss/dkappa of the next output row
 
   for (int k = 0; k < K; ++k) {
     T mu0[9];
+    if constexpr (W1) {
+      mf.feed(mun, mu0);
+    } else {
 #pragma unroll
-    for (int l = 0; l < 9; ++l) mu0[l] = mun[l];
+      for (int l = 0; l < 9; ++l) mu0[l] = mun[l];
+    }
     const T h = hn, jx = jxn, jy = jyn, kap = kn;
     const int rn = (ry + 1 == ny) ? 0 : ry + 1;
     if (k + 1 < K) load_row(rn);
@@ -367,10 +473,16 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
     if (k >= 4) {
       // output row y = r-2
       const int y = y0 + (k - 4);
-      T lam[9];
       double gt;
-      S.out(mu2, lam, gt, C);
-      store_lambda(A, L, y, lam);
+      if constexpr (W1) {
+        T lh, ljx, ljy;
+        S.out_moments(mu2, lh, ljx, ljy, gt, C);
+        store_fields(A, L, y, lh, ljx, ljy);
+      } else {
+        T lam[9];
+        S.out(mu2, lam, gt, C);
+        store_lambda(A, L, y, lam);
+      }
       double g = gkn;
       if (k + 1 < K) gkn = ld_f64(gk_row(A, y + 1), L.gk);
       if (L.out) g += gt;
@@ -395,8 +507,9 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
 // the two terms in the order of two single steps.  The workgroup is a single
 // wavefront, so the ring needs no barrier between wavefronts.  Strips are
 // kAdjW columns plus five halo columns per side (two per stage plus the
-// one-column shift between them); rows y0-5 .. yend+4 are read.
-template <typename T, bool KF>
+// one-column shift between them); rows y0-5 .. yend+4 are read (W1: the
+// fields of rows y0-6 .. yend+5).
+template <typename T, bool KF, bool W1 = false>
 __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
   __shared__ T ring[5][9][64];
   __shared__ double gring[4][64];
@@ -429,21 +542,37 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
   const int K = (yend - y0) + 10;
   AdjIn<T> ia, ib;
   AdjCap<T> ca = {}, cb = {};
+  // W1: mu of row r needs the fields of rows r-1 .. r+1; they are read one
+  // row ahead (into in.mu) and fed into `mf`, which completes mu of the row
+  // before
+  MuFromFields<T> mf;
   auto load1 = [&](int k, AdjIn<T> &in) {
     const int row = wrap(y0 - 5 + k, ny);
-    load_mu(A, L, row, in.mu);
+    if constexpr (W1) load_fields(A, L, row + 1 == ny ? 0 : row + 1, in.mu);
+    else load_mu(A, L, row, in.mu);
     load_cap(A, A.cap, L, row, in.h, in.jx, in.jy);
     in.kap = C.kap0;
     if constexpr (KF) in.kap = load_kap(A, L, row);
   };
+  if constexpr (W1) {
+    T v[9], unused[9];
+    load_fields(A, L, wrap(y0 - 6, ny), v);
+    mf.feed(v, unused);
+    load_fields(A, L, wrap(y0 - 5, ny), v);
+    mf.feed(v, unused);
+  }
   load1(0, ia);
   load1(1, ib);
   double gkn = ld_f64(gk_row(A, y0), L.gk);  // dLoss/dkappa of the next output row
 
   auto iteration = [&](int k, AdjIn<T> &in, AdjCap<T> &cin) {
     T mu0[9];
+    if constexpr (W1) {
+      mf.feed(in.mu, mu0);
+    } else {
 #pragma unroll
-    for (int l = 0; l < 9; ++l) mu0[l] = in.mu[l];
+      for (int l = 0; l < 9; ++l) mu0[l] = in.mu[l];
+    }
     const T h = in.h, jx = in.jx, jy = in.jy, kap = in.kap;
     const T h_2 = cin.h, jx_2 = cin.jx, jy_2 = cin.jy, kap_2 = kd3;
     kd3 = kd2;
@@ -456,7 +585,14 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
     if (k >= 4) {
       T lam[9];
       double gt;
-      S1.out(mu2, lam, gt, C);
+      if constexpr (W1) {
+        T lh, ljx, ljy;
+        S1.out_moments(mu2, lh, ljx, ljy, gt, C);
+#pragma unroll
+        for (int l = 0; l < 9; ++l) lam[l] = lam_of(l, lh, ljx, ljy);
+      } else {
+        S1.out(mu2, lam, gt, C);
+      }
       const int s = k % 5;
 #pragma unroll
       for (int l = 0; l < 9; ++l) ring[s][l][lane] = lam[l];
@@ -484,10 +620,16 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
 #pragma unroll
         for (int l = 0; l < 9; ++l)
           mo[l] = ring[(k - 3 + kCy[l]) % 5][l][kCx[l] == 0 ? lane : (kCx[l] > 0 ? le : lw)];
-        T lam[9];
         double gt;
-        S2.out(mo, lam, gt, C);
-        store_lambda(A, L, y, lam);
+        if constexpr (W1) {
+          T lh, ljx, ljy;
+          S2.out_moments(mo, lh, ljx, ljy, gt, C);
+          store_fields(A, L, y, lh, ljx, ljy);
+        } else {
+          T lam[9];
+          S2.out(mo, lam, gt, C);
+          store_lambda(A, L, y, lam);
+        }
         double g = gkn;
         if (k + 1 < K) gkn = ld_f64(gk_row(A, y + 1), L.gk);
         if (L.out) {
@@ -509,12 +651,23 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
 // nu_l(x, y) = lambda^N_l(x, y + c_ly) = dLoss/dh_N(x, y + c_ly) for every l
 // (h_N = sum_l f_l); dLoss/dkappa = 0, its padding included.  Thread i of a
 // row: entry i of the row's dLoss/dkappa records, and column i if i < nx.
-template <typename T>
+// W1: lambda_h = dLoss/dh_N, lambda_j = 0 (so lambda_l = dLoss/dh_N for
+// every l); thread i writes slot i of the row's field records, padding
+// included.
+template <typename T, bool W1 = false>
 __global__ void adj_seed_kernel(AdjArgs A, const double *grad_h) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (i >= A.nstrips * 64) return;
   ((double *)(A.gk + (size_t)y * A.nstrips * kGkRB))[i] = 0.0;
+  if constexpr (W1) {
+    const int s = i / 64, slot = i - 64 * s, x = s * kAdjW + slot;
+    T *rec = (T *)(A.dst + ((size_t)y * A.nstrips + s) * AdjRec1<T>::RB);
+    rec[slot] = slot < kAdjW && x < A.nx ? (T)grad_h[(size_t)y * A.nx + x] : T(0);
+    rec[64 + slot] = T(0);
+    rec[128 + slot] = T(0);
+    return;
+  }
   if (i >= A.nx) return;
   const int s = i / kAdjW;
   char *ent = A.dst + ((size_t)y * A.nstrips + s) * AdjRec<T>::RB + (size_t)(i - s * kAdjW) * sizeof(T);
@@ -524,9 +677,10 @@ __global__ void adj_seed_kernel(AdjArgs A, const double *grad_h) {
   }
 }
 
-// dLoss/dh0 = sum_l lambda^0_l dE_l/dh0 with lambda^0_l(x, y) = nu_l(x, y - c_ly);
+// dLoss/dh0 = sum_l lambda^0_l dE_l/dh0 with lambda^0_l(x, y) = nu_l(x, y - c_ly)
+// (W1: lam_of the fields at (x, y));
 // dLoss/dtheta = dLoss/dkappa * (n-1)(m-1)/((n-m) h_*) * sin(theta).
-template <typename T>
+template <typename T, bool W1 = false>
 __global__ void adj_finish_kernel(AdjArgs A, const double *h0, const double *theta, double theta0, double kconst,
                                   double *grad_h0, double *grad_theta) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -537,10 +691,18 @@ __global__ void adj_finish_kernel(AdjArgs A, const double *h0, const double *the
   if (grad_h0) {
     const double h = h0[od];
     const size_t ent = (size_t)st * AdjRec<T>::RB + (size_t)pos * sizeof(T);
+    T fh = 0, fx = 0, fy = 0;
+    if constexpr (W1) {
+      const T *rec = (const T *)(A.src + ((size_t)y * A.nstrips + st) * AdjRec1<T>::RB);
+      fh = rec[pos];
+      fx = rec[64 + pos];
+      fy = rec[128 + pos];
+    }
     double s = 0.0;
     for (int l = 0; l < 9; ++l) {
       const int ys = wrap(y - kCy[l], A.ny);
-      const double lam = (double)*(const T *)(A.src + (size_t)ys * A.nstrips * AdjRec<T>::RB + ent + AdjRec<T>::seg(l));
+      const double lam = W1 ? (double)lam_of(l, fh, fx, fy)
+                            : (double)*(const T *)(A.src + (size_t)ys * A.nstrips * AdjRec<T>::RB + ent + AdjRec<T>::seg(l));
       const double dE = l == 0 ? 1.0 - A.g * h * (5.0 / 3.0) : ((l & 1) ? A.g * h / 3.0 : A.g * h / 12.0);
       s += lam * dE;
     }
@@ -553,59 +715,70 @@ __global__ void adj_finish_kernel(AdjArgs A, const double *h0, const double *the
   }
 }
 
-template <typename T>
+template <typename T, bool W1>
 static hipError_t adj_step_t(const AdjArgs &B, bool kf, int ns, hipStream_t s) {
   const dim3 grid(8 * B.per_xcd), block(64);
   if (ns == 2) {
-    if (kf) adj_step2_kernel<T, true><<<grid, block, 0, s>>>(B);
-    else adj_step2_kernel<T, false><<<grid, block, 0, s>>>(B);
+    if (kf) adj_step2_kernel<T, true, W1><<<grid, block, 0, s>>>(B);
+    else adj_step2_kernel<T, false, W1><<<grid, block, 0, s>>>(B);
   } else {
-    if (kf) adj_step_kernel<T, true><<<grid, block, 0, s>>>(B);
-    else adj_step_kernel<T, false><<<grid, block, 0, s>>>(B);
+    if (kf) adj_step_kernel<T, true, W1><<<grid, block, 0, s>>>(B);
+    else adj_step_kernel<T, false, W1><<<grid, block, 0, s>>>(B);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_adj_step(int prec, const AdjArgs &B, bool kf, int ns, hipStream_t s) {
-  return prec == kF64 ? adj_step_t<double>(B, kf, ns, s) : adj_step_t<float>(B, kf, ns, s);
+hipError_t launch_adj_step(int prec, const AdjArgs &B, bool kf, int ns, bool w1, hipStream_t s) {
+  if (prec == kF64) return w1 ? adj_step_t<double, true>(B, kf, ns, s) : adj_step_t<double, false>(B, kf, ns, s);
+  return w1 ? adj_step_t<float, true>(B, kf, ns, s) : adj_step_t<float, false>(B, kf, ns, s);
 }
 
-template <typename T>
+template <typename T, bool W1>
 static int adj_occupancy_t(bool kf, int ns) {
   int n = 0;
   hipError_t e;
   if (ns == 2)
-    e = kf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_step2_kernel<T, true>, 64, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_step2_kernel<T, false>, 64, 0);
+    e = kf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_step2_kernel<T, true, W1>, 64, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_step2_kernel<T, false, W1>, 64, 0);
   else
-    e = kf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_step_kernel<T, true>, 64, 0)
-           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_step_kernel<T, false>, 64, 0);
+    e = kf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_step_kernel<T, true, W1>, 64, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_step_kernel<T, false, W1>, 64, 0);
   return e == hipSuccess ? n : 0;
 }
 
-int adj_blocks_per_cu(int prec, bool kf, int ns) {
-  return prec == kF64 ? adj_occupancy_t<double>(kf, ns) : adj_occupancy_t<float>(kf, ns);
+int adj_blocks_per_cu(int prec, bool kf, int ns, bool w1) {
+  if (prec == kF64) return w1 ? adj_occupancy_t<double, true>(kf, ns) : adj_occupancy_t<double, false>(kf, ns);
+  return w1 ? adj_occupancy_t<float, true>(kf, ns) : adj_occupancy_t<float, false>(kf, ns);
 }
 
-hipError_t launch_adj_seed(int prec, const AdjArgs &B, const double *grad_h, hipStream_t s) {
+hipError_t launch_adj_seed(int prec, const AdjArgs &B, const double *grad_h, bool w1, hipStream_t s) {
   const dim3 block(256), grid((B.nstrips * 64 + 255) / 256, B.ny);
-  if (prec == kF64) adj_seed_kernel<double><<<grid, block, 0, s>>>(B, grad_h);
-  else adj_seed_kernel<float><<<grid, block, 0, s>>>(B, grad_h);
+  if (prec == kF64) {
+    if (w1) adj_seed_kernel<double, true><<<grid, block, 0, s>>>(B, grad_h);
+    else adj_seed_kernel<double, false><<<grid, block, 0, s>>>(B, grad_h);
+  } else {
+    if (w1) adj_seed_kernel<float, true><<<grid, block, 0, s>>>(B, grad_h);
+    else adj_seed_kernel<float, false><<<grid, block, 0, s>>>(B, grad_h);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_adj_finish(int prec, const AdjArgs &B, const double *h0, const double *theta, double theta0,
-                             double kconst, double *grad_h0, double *grad_theta, hipStream_t s) {
+                             double kconst, double *grad_h0, double *grad_theta, bool w1, hipStream_t s) {
   const dim3 block(256), grid((B.nx + 255) / 256, B.ny);
-  if (prec == kF64)
-    adj_finish_kernel<double><<<grid, block, 0, s>>>(B, h0, theta, theta0, kconst, grad_h0, grad_theta);
-  else
-    adj_finish_kernel<float><<<grid, block, 0, s>>>(B, h0, theta, theta0, kconst, grad_h0, grad_theta);
+  if (prec == kF64) {
+    if (w1) adj_finish_kernel<double, true><<<grid, block, 0, s>>>(B, h0, theta, theta0, kconst, grad_h0, grad_theta);
+    else adj_finish_kernel<double, false><<<grid, block, 0, s>>>(B, h0, theta, theta0, kconst, grad_h0, grad_theta);
+  } else {
+    if (w1) adj_finish_kernel<float, true><<<grid, block, 0, s>>>(B, h0, theta, theta0, kconst, grad_h0, grad_theta);
+    else adj_finish_kernel<float, false><<<grid, block, 0, s>>>(B, h0, theta, theta0, kconst, grad_h0, grad_theta);
+  }
   return hipGetLastError();
 }
 
 static size_t adj_buf_bytes(const tflbm_sim *s) {
-  const size_t rb = s->p.prec == kF64 ? AdjRec<double>::RB : AdjRec<float>::RB;
+  const size_t rb = s->w1 ? (s->p.prec == kF64 ? AdjRec1<double>::RB : AdjRec1<float>::RB)
+                          : (s->p.prec == kF64 ? AdjRec<double>::RB : AdjRec<float>::RB);
   return (size_t)s->p.ny * s->adj_nstrips * rb;
 }
 static size_t gk_bytes(const tflbm_sim *s) { return (size_t)s->p.ny * s->adj_nstrips * kGkRB; }
@@ -665,7 +838,7 @@ int tflbm_adj_seed(tflbm_sim *sim, void *d_adj, const double *d_grad_h, tflbm_st
   }
   sim->adj_cur = 1;  // seed writes the "dst" of a cur=1 state, i.e. the first buffer
   AdjArgs B = make_adj_args(sim, d_adj);
-  const int rc = hip_status(sim, launch_adj_seed(sim->p.prec, B, d_grad_h, (hipStream_t)stream));
+  const int rc = hip_status(sim, launch_adj_seed(sim->p.prec, B, d_grad_h, sim->w1, (hipStream_t)stream));
   if (rc) return rc;
   sim->adj_cur = 0;
   sim->adj_seeded = true;
@@ -677,7 +850,7 @@ int tflbm_adj_step(tflbm_sim *sim, void *d_adj, const void *d_capture_t, tflbm_s
   if (!sim->adj_seeded) return TFLBM_ESTATE;
   AdjArgs B = make_adj_args(sim, d_adj);
   B.cap = (const char *)d_capture_t;
-  const int rc = hip_status(sim, launch_adj_step(sim->p.prec, B, sim->kfield == kKappa, 1, (hipStream_t)stream));
+  const int rc = hip_status(sim, launch_adj_step(sim->p.prec, B, sim->kfield == kKappa, 1, sim->w1, (hipStream_t)stream));
   if (rc) return rc;
   sim->adj_cur ^= 1;
   return TFLBM_OK;
@@ -695,7 +868,7 @@ int tflbm_adj_steps(tflbm_sim *sim, void *d_adj, const void *d_capture, int64_t 
     AdjArgs B = make_adj_args(sim, d_adj, ns);
     B.cap = cap + (size_t)t * cb;
     B.cap2 = ns == 2 ? cap + (size_t)(t - 1) * cb : nullptr;
-    const int rc = hip_status(sim, launch_adj_step(sim->p.prec, B, sim->kfield == kKappa, ns, (hipStream_t)stream));
+    const int rc = hip_status(sim, launch_adj_step(sim->p.prec, B, sim->kfield == kKappa, ns, sim->w1, (hipStream_t)stream));
     if (rc) return rc;
     sim->adj_cur ^= 1;
     t -= ns;
@@ -710,7 +883,7 @@ int tflbm_adj_finish(tflbm_sim *sim, const void *d_adj, const double *d_h0, cons
   if (!sim->adj_seeded) return TFLBM_ESTATE;
   AdjArgs B = make_adj_args(sim, (void *)d_adj);
   return hip_status(sim, launch_adj_finish(sim->p.prec, B, d_h0, d_theta, sim->p.theta0, sim->kconst, d_grad_h0,
-                                           d_grad_theta, (hipStream_t)stream));
+                                           d_grad_theta, sim->w1, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -127,8 +127,8 @@ void plan_launches(tflbm_sim *s) {
   // Reverse steps: at most two resident wavefronts per SIMD are planned for
   // (eight per CU).  At 4096^2 FP32 the one-step kernel, which fits three,
   // ran 9% faster with chunks sized for two than for three.
-  int aocc1 = adj_blocks_per_cu(s->p.prec, s->kfield == kKappa, 1);
-  int aocc2 = adj_blocks_per_cu(s->p.prec, s->kfield == kKappa, 2);
+  int aocc1 = adj_blocks_per_cu(s->p.prec, s->kfield == kKappa, 1, s->w1);
+  int aocc2 = adj_blocks_per_cu(s->p.prec, s->kfield == kKappa, 2, s->w1);
   aocc1 = aocc1 <= 0 || aocc1 > 8 ? 8 : aocc1;
   aocc2 = aocc2 <= 0 || aocc2 > 8 ? 8 : aocc2;
   s->adj_rows = choose_rows(ny, s->adj_nstrips, aocc1 * cus, kMinRowsAdj, "TFLBM_ADJ_ROWS");
@@ -145,7 +145,13 @@ void plan_launches(tflbm_sim *s) {
   // fused pass from 768^2 on (15.6 vs 20.1; 4096^2: 256 vs 446); at FP64 the
   // two tie at 512^2 (16.9 us) and the fused pass wins from 768^2 on (25.9
   // vs 31.8).
-  s->adj_fuse_fits = (int64_t)s->adj_nstrips * ((ny + kMinRowsAdj2 - 1) / kMinRowsAdj2) > (int64_t)aocc2 * cus;
+  // With omega = 1 the FP64 one-step pass, which carries three fields per
+  // site, runs two wavefronts per SIMD where the two-step pass runs one, and
+  // is as fast or faster at every size (per step: 1024^2 33.6 vs 33.3 us,
+  // 2048^2 104.0 vs 111.3, 4096^2 393.6 vs 407.4); FP32 keeps two steps per
+  // pass (4096^2: 188.8 vs 284.8 us).
+  s->adj_fuse_fits = !(s->w1 && s->p.prec == kF64) &&
+                     (int64_t)s->adj_nstrips * ((ny + kMinRowsAdj2 - 1) / kMinRowsAdj2) > (int64_t)aocc2 * cus;
   s->graphs = (int64_t)s->p.nx * ny <= kGraphMaxSites;
   if (const char *e = std::getenv("TFLBM_GRAPH")) s->graphs = std::atoi(e) != 0;
 }
@@ -361,8 +367,7 @@ static int steps_per_pass(const tflbm_sim *sim) {
 
 static int launch_steps(tflbm_sim *sim, int64_t nsteps, void *d_capture, hipStream_t st) {
   const size_t cap_bytes = tflbm_capture_bytes(sim);
-  int ns_max = steps_per_pass(sim);
-  if (d_capture && ns_max > 2) ns_max = 2;  // captures run at most two steps per pass
+  const int ns_max = steps_per_pass(sim);
   int64_t i = 0;
   while (i < nsteps) {
     const int ns = (int)(nsteps - i < ns_max ? nsteps - i : ns_max);

@@ -1147,13 +1147,8 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s) 
 template <int P, int NS, bool G0, int KF, bool W1>
 static void launch_step_k(const StepArgs &A, bool cap, hipStream_t s) {
   const dim3 grid(8 * A.per_xcd), block(64);
-  if constexpr (NS <= 2) {  // captures run at most two steps per pass
-    if (cap) {
-      step_kernel<P, KF, true, NS, G0, W1><<<grid, block, 0, s>>>(A);
-      return;
-    }
-  }
-  step_kernel<P, KF, false, NS, G0, W1><<<grid, block, 0, s>>>(A);
+  if (cap) step_kernel<P, KF, true, NS, G0, W1><<<grid, block, 0, s>>>(A);
+  else step_kernel<P, KF, false, NS, G0, W1><<<grid, block, 0, s>>>(A);
 }
 
 template <int P, int NS, bool G0, bool W1>
@@ -1186,7 +1181,7 @@ static hipError_t launch_step_ns(int ns, const StepArgs &A, int kf, bool cap, hi
 }
 
 hipError_t launch_step(int prec, int ns, const StepArgs &A, int kf, bool cap, bool w1, hipStream_t s) {
-  if (ns < 1 || ns > max_steps_per_pass(prec, w1) || (cap && ns > 2)) return hipErrorInvalidValue;
+  if (ns < 1 || ns > max_steps_per_pass(prec, w1)) return hipErrorInvalidValue;
   switch (prec) {
     case kF64: return w1 ? launch_step_ns<kF64, true>(ns, A, kf, cap, s) : launch_step_ns<kF64, false>(ns, A, kf, cap, s);
     case kF32: return w1 ? launch_step_ns<kF32, true>(ns, A, kf, cap, s) : launch_step_ns<kF32, false>(ns, A, kf, cap, s);

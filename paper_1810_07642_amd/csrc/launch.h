@@ -20,7 +20,6 @@ int record_bytes(int prec);
 // t + ns).  kfield: the per-site field the step reads: 0 none, 1 kappa, 2 the
 // pairs (-gamma/6, -gamma kappa) of a position-dependent surface tension.
 // w1: omega = 1 (tau = 1), the stages without a population history.
-// Captures run at most two steps per pass.
 hipError_t launch_step(int prec, int ns, const StepArgs &A, int kfield, bool capture, bool w1, hipStream_t s);
 // Most fused steps per pass of a storage form: its halo columns allow three
 // per step, and three need the omega = 1 stages.
@@ -37,11 +36,12 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // Reverse-mode kernels.
 struct AdjArgs;
-hipError_t launch_adj_seed(int prec, const AdjArgs &B, const double *grad_h, hipStream_t s);
-hipError_t launch_adj_step(int prec, const AdjArgs &B, bool kfield, int ns, hipStream_t s);
+// w1: omega = 1, the adjoint carried between steps as three fields per site.
+hipError_t launch_adj_seed(int prec, const AdjArgs &B, const double *grad_h, bool w1, hipStream_t s);
+hipError_t launch_adj_step(int prec, const AdjArgs &B, bool kfield, int ns, bool w1, hipStream_t s);
 hipError_t launch_adj_finish(int prec, const AdjArgs &B, const double *h0, const double *theta, double theta0,
-                             double kconst, double *grad_h0, double *grad_theta, hipStream_t s);
+                             double kconst, double *grad_h0, double *grad_theta, bool w1, hipStream_t s);
 int adj_record_columns();
-int adj_blocks_per_cu(int prec, bool kfield, int ns);
+int adj_blocks_per_cu(int prec, bool kfield, int ns, bool w1);
 
 }  // namespace tflbm

@@ -50,9 +50,12 @@ STEP_KERNEL = {"fp64": ("step_kernel<0, 1, false, 3, false, true>", 3),
                "fp32": ("step_kernel<1, 1, false, 3, false, true>", 3),
                "fp16s": ("step_kernel<2, 1, false, 2, true, true>", 2)}
 PROFILE_STEPS = 24  # a multiple of 2 and of 3: whole passes of the kernel
-# The two-step reverse pass (FP32 adjoint): adjoint 36 + two captures 24 +
-# kappa 4 + g_kappa 8 read; adjoint 36 + g_kappa 8 written.
-ADJ_BYTES = (72, 44)
+# The two-step reverse pass of the benchmark workload (tau = 1: the adjoint
+# between steps as three fields per site), FP32: fields 12 + two captures 24 +
+# kappa 4 + g_kappa 8 read; fields 12 + g_kappa 8 written.  (The general pass
+# moves nine adjoint populations: 72 read, 44 written.)
+ADJ_BYTES = (48, 20)
+ADJ_KERNEL = "adj_step2_kernel<float, true, true>"
 CALIB_BYTES = 1 << 30  # the 1 GiB calibration copy
 CLOCK_GHZ = 2.4
 SIMDS = 256 * 4
@@ -290,10 +293,12 @@ def main(argv=None):
             cmds.append(args.sq_command)
         text = traffic_summary(
             "Reverse pass, two steps per launch: FP32 adjoint, patterned dewetting 4096 x 4096",
-            "FP32 adjoint, kappa field, two reverse time steps per launch", r"adj_step2_kernel<float, true>",
+            "FP32 adjoint carried as three fields per site (tau = 1), kappa field, two reverse time steps per "
+            "launch", re.escape(ADJ_KERNEL),
             args.fetch, args.write, ADJ_BYTES[0] * N4096, ADJ_BYTES[1] * N4096, 2, ADJ_SOURCES, cmds, sq_dir=args.sq,
             trace_dir=args.trace,
-            alg_desc="adjoint 36 + two captures 24 + kappa 4 + g_kappa 8 read; adjoint 36 + g_kappa 8 written (B/site)",
+            alg_desc="adjoint fields 12 + two captures 24 + kappa 4 + g_kappa 8 read; fields 12 + g_kappa 8 written "
+                     "(B/site)",
             notes=["`bench.py --profile-adjoint 16` captures 16 FP32 steps of the benchmark workload, runs the "
                    "reverse pass over them (8 launches of the two-step kernel), then a 1 GiB runtime copy that "
                    "calibrates the counters."])

@@ -94,8 +94,11 @@ def test_workspace_and_state_sizes(lib, prec, per_site):
     # adjoint: two buffers of records of 54 columns (nine segments padded to an
     # odd number of lines) and FP64 dLoss/dkappa records of 64 values, each
     # rounded to 4 KiB
+    # (with tau = 1, three fields per site in records of 3 x 64 slots)
     ARB = {0: 31 * 128, 1: 17 * 128, 2: 17 * 128}[prec]
     assert ARB >= 9 * 54 * wb
+    if p.tau == 1.0:
+        ARB = 3 * 64 * wb
     nas = -(-100 // 54)
     r4k = lambda v: -(-v // 4096) * 4096
     assert lib.tflbm_adj_bytes(h) == 2 * r4k(30 * nas * ARB) + r4k(30 * nas * 512)

@@ -257,6 +257,41 @@ def test_two_steps_per_pass_equal_single_steps_bitwise(prec, shape, rows2, field
         assert nd == 0, name
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
+@pytest.mark.parametrize("shape,rows2,field,nsteps", [
+    ((150, 173), "7", True, 7),
+    ((45, 70), None, False, 6),
+    ((3, 2), None, True, 5),
+    ((64, 131), None, True, 9),
+])
+def test_omega1_reverse_pass_equals_general_bitwise(prec, shape, rows2, field, nsteps, monkeypatch):
+    """At tau = 1 the step's adjoint is lambda_h + c_l . lambda_j, and the
+    library carries three fields per site between reverse steps instead of
+    nine populations.  Against the general reverse pass (TFLBM_OMEGA1=0), both
+    with two reverse steps per pass and with one per pass: the same bits."""
+    ny, nx = shape
+    banner(f"omega = 1 reverse pass vs general: {prec} {ny}x{nx}, {nsteps} steps, rows {rows2}, field {field}")
+    monkeypatch.setenv("TFLBM_ADJ_FUSE", "2")
+    if rows2 is not None:
+        monkeypatch.setenv("TFLBM_ADJ_ROWS2", rows2)
+    h0, th = random_case(ny, nx, 79)
+    p = dict(tau=1.0, gamma=0.02, g=1e-3, hstar=0.15, delta=0.8, ax=2e-5, ay=-1e-5)
+    if prec != "fp64":
+        p["href"] = 0.45
+    g = torch.Generator().manual_seed(80)
+    grad_h = torch.randn((ny, nx), generator=g, dtype=torch.float64)
+    runs = []
+    for omega1 in ("1", "0"):
+        monkeypatch.setenv("TFLBM_OMEGA1", omega1)
+        for fused in (True, False):
+            runs.append(_reverse_pass(prec, h0, th, p, nsteps, grad_h, fused, field))
+    for other in runs[1:]:
+        for x, y, name in ((other[0], runs[0][0], "dL/dh0"), (other[1], runs[0][1], "dL/dtheta")):
+            assert torch.isfinite(y).all(), name
+            nd = int((x != y).sum())
+            assert nd == 0, (name, nd, float((x - y).abs().max()))
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_keeping_every_capture_equals_checkpoint_and_recompute(prec):
     """K = 0 keeps the captures the forward writes instead of checkpoints and
