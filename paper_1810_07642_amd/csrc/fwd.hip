@@ -973,6 +973,19 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
     }
     if (k < K) iteration(k, fa, fb, ka);
   } else {
+    // one row ahead (three steps): FP32 in groups of six rows, so that the
+    // stages' row histories keep their registers (a third fewer moves, +1 %);
+    // FP64 unrolled would need more than 256 VGPRs
+    if constexpr (P == kF32) {
+      for (; k + 5 < K; k += 6) {
+        iteration(k, fa, fa, ka);
+        iteration(k + 1, fa, fa, ka);
+        iteration(k + 2, fa, fa, ka);
+        iteration(k + 3, fa, fa, ka);
+        iteration(k + 4, fa, fa, ka);
+        iteration(k + 5, fa, fa, ka);
+      }
+    }
     for (; k < K; ++k) iteration(k, fa, fa, ka);
   }
 
