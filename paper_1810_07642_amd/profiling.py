@@ -36,7 +36,7 @@ CSRC = os.path.join(PKG, "csrc")
 
 # Sources a kernel's traffic depends on: the kernel and the launch plan that
 # sets its tiles (hence its halo re-reads).
-STEP_SOURCES = [os.path.join(CSRC, f) for f in ("fwd.hip", "device.h", "api.hip")]
+STEP_SOURCES = [os.path.join(CSRC, f) for f in ("step.h", "step_form.hip", "fwd.hip", "device.h", "api.hip")]
 ADJ_SOURCES = [os.path.join(CSRC, f) for f in ("adj.hip", "device.h", "api.hip")]
 
 N4096 = 4096 * 4096
