@@ -468,9 +468,42 @@ __device__ __forceinline__ unsigned int enc16x2(float a, float b, float qscale) 
   return __builtin_bit_cast(unsigned int, w);
 }
 
+// A buffer offset past every row: an access there is dropped by the buffer
+// range check and touches no memory.
+constexpr int kStoreDrop = 0x7fff0000;
+
+// Uniform stores.  The counter a wavefront waits on for its loads also counts
+// its stores and retires both in issue order, and the compiler sizes each
+// wait for the path through the loop with the fewest memory instructions
+// after the load.  A row iteration whose stores are skipped on some path (a
+// lane mask that may be empty, a stage that has not started emitting) makes
+// the wait for the next prefetched row drain the stores just issued, so every
+// row pays the latency of its own stores.  With UNI, store_row issues the
+// same stores on every path (lanes that store nothing aim at kStoreDrop), the
+// iterations before the first stored row issue as many dropped stores
+// (drop_row_stores), and the row loop tells the compiler which iterations
+// store: the wait for a row then leaves the previous row's stores in flight.
+// Measured (FP64 MLUPS, bitwise the same results): three omega = 1 steps per
+// pass at 4096^2 72.4k -> 77.9k, at 2048^2 63.6k -> 69.8k; the general stages
+// (two steps) at 4096^2 54.5k -> 57.9k.  Left out where it lost: the one- and
+// two-step omega = 1 kernels of small lattices, whose tiles are bound by their
+// chain of rows (256^2 10.3k -> 9.1k), and FP32 and FP16S, whose VALU fills
+// more of the wait (2 % and 5 % slower: more registers, FP16S spills); the
+// capture and surface tension kernels would spill.
+template <int P> __device__ __forceinline__ void drop_row_stores(const StepArgs &A) {
+  static_assert(P == kF64, "uniform stores are built for FP64 records");
+  // byte stores at distinct offsets: a store of this width occurs nowhere
+  // else, so the compiler neither merges these with a row's stores nor drops
+  // them as duplicates
+  const rsrc_t none = make_rsrc(A.dst, 0);
+#pragma unroll
+  for (int i = 0; i < 12; ++i) __builtin_amdgcn_raw_buffer_store_b8((unsigned char)0, none, kStoreDrop + 4 * i, 0, kStorePolicy);
+}
+
 // Stores the post-collision deviations of row y (values at the lane's own
-// columns, hv = dh of the row) into stored column x of rows y + c_ly.
-template <int P, bool G0 = false>
+// columns, hv = dh of the row) into stored column x of rows y + c_ly; UNI:
+// uniform stores (above), FP64 only.
+template <int P, bool G0 = false, bool UNI = false>
 __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typename Form<P>::T (&post)[9][Form<P>::V],
                                           const typename Form<P>::T (&hv)[Form<P>::V], const Lane<P> &L, int x0,
                                           int xend, int lane) {
@@ -484,6 +517,20 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
   const rsrc_t rowD[3] = {make_rsrc(A.dst + yS * rowB, (uint32_t)rowB), make_rsrc(A.dst + y * rowB, (uint32_t)rowB),
                           make_rsrc(A.dst + yN * rowB, (uint32_t)rowB)};  // indexed by c_ly + 1
   const bool pair = L.pair;
+  static_assert(!UNI || P == kF64, "uniform stores are built for FP64 records");
+  if constexpr (UNI) {
+    // nine stores and three padding stores on every path
+    const int oe = L.out[0] ? L.oe[0] : kStoreDrop;  // one column per lane: pair == out[0]
+#pragma unroll
+    for (int l = 0; l < 9; ++l) st_f64(rowD[kCy[l] + 1], oe + seg_offset<P>(l), post[l][0]);
+    const bool full = xend - x0 == B;
+    const int rec = (x0 / B) * RB;
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+      st_f32(rowD[g == 0 ? 1 : (g == 1 ? 2 : 0)],
+             full && 4 * lane < pad_bytes<P>(g) ? rec + pad_offset<P>(g) + 4 * lane : kStoreDrop, 0.f);
+    return;
+  }
   if constexpr (P == kF16S) {
     // the site's height deviation s, and each moving population as its FP16
     // difference from the rest equilibrium e_l(s) of this (its source) site,
@@ -736,8 +783,8 @@ template <typename T, int V> struct Handoff {
 // A.capture, step t + s s capture blocks later.
 // G0 (FP16S only): the launch has g = 0, so the rest equilibrium of the
 // FP16S shift has no moving part and its code is left out.
-// W1: omega = 1, the stages keep no populations (Stage) and the kernel no
-// LDS, which lets three fused steps keep eight wavefronts per CU.
+// W1: omega = 1, the stages keep no populations (Stage), only j of two rows
+// in LDS, which lets three fused steps keep eight wavefronts per CU.
 template <int P, int KF, bool CAP, int NS, bool G0 = false, bool W1 = false>
 __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   using T = typename Form<P>::T;
@@ -806,6 +853,11 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
 
   constexpr int HALO = 2 + 3 * (NS - 1);
   const int K = (yend - y0) + 2 * HALO;
+  // uniform stores (store_row) and KST, the first row iteration whose last
+  // stage stores a row (each stage emits from its fifth row on, and stage s
+  // starts six rows after stage s - 1)
+  constexpr bool UNI = P == kF64 && !CAP && KF != kGammaKappa && (NS == 3 || !W1);
+  constexpr int KST = 4 + 6 * (NS - 1);
   auto rsrc_src = [&](int row) { return make_rsrc(A.src + row * rowB, (uint32_t)rowB); };
   int ry = wrap(y0 - HALO, ny);                          // row r of stage 0
   // rows are loaded PF rows ahead of their use.  Measured at 4096^2 (MLUPS,
@@ -858,6 +910,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
     load_buf(rsrc_src(r2), fc);
     if constexpr (KF != kNoField) load_kappa<P, KF>(rsrc_kap(r2), L, kc);
   }
+  if constexpr (UNI) drop_row_stores<P>(A);  // as a row iteration leaves behind its loads
   if constexpr (P == kF16S) {
     // the c_ly = +1 values of the first row, which fp16s_decode otherwise
     // carries over from the row before
@@ -894,11 +947,14 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
     // row need not drain the loads of the rows after it.
     load_buf(k + PF < KL ? rsrc_src(rpre) : make_rsrc(A.src, 0), cur);
     if constexpr (KF != kNoField) load_kappa<P, KF>(k + PF < KL ? rsrc_kap(rpre) : make_rsrc(A.kfield, 0), L, kcur);
+    if constexpr (UNI) {
+      if (k < KST) drop_row_stores<P>(A);
+    }
     T post[9][V], hv[V], jxv[V], jyv[V];
     if (S0.finish(k, f2, post, hv, jxv, jyv, C, L, bad)) {
       const int q = y0 - HALO + k - 2;  // row of the post-collision values (unwrapped)
       if constexpr (NS == 1) {
-        store_row<P, G0>(A, q, post, hv, L, x0, xend, lane);
+        store_row<P, G0, UNI>(A, q, post, hv, L, x0, xend, lane);
         if constexpr (CAP) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane);
       } else {
         const int e = k - 4;  // emission index of stage 0
@@ -916,7 +972,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
           if (S1.finish(j, g2, post2, hv2, jx2, jy2, C, L, bad)) {
             const int q1 = y0 - HALO + 1 + j;  // row of stage 1's post-collision values
             if constexpr (NS == 2) {
-              store_row<P, G0>(A, q1, post2, hv2, L, x0, xend, lane);
+              store_row<P, G0, UNI>(A, q1, post2, hv2, L, x0, xend, lane);
               if constexpr (CAP) capture_row<P>(A, A.capture + capblk, q1, hv2, jx2, jy2, L, C.href, x0, xend, lane);
             } else {
               const int e1 = j - 4;  // emission index of stage 1
@@ -934,7 +990,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
                 T post3[9][V], hv3[V], jx3[V], jy3[V];
                 if (S2.finish(j2, g4, post3, hv3, jx3, jy3, C, L, bad)) {
                   const int q2 = y0 - HALO + 4 + j2;
-                  store_row<P, G0>(A, q2, post3, hv3, L, x0, xend, lane);
+                  store_row<P, G0, UNI>(A, q2, post3, hv3, L, x0, xend, lane);
                   if constexpr (CAP)
                     capture_row<P>(A, A.capture + 2 * capblk, q2, hv3, jx3, jy3, L, C.href, x0, xend, lane);
                 }
@@ -986,9 +1042,23 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
     if (k < K) iteration(k, fa, fb, ka);
     if (k + 1 < K) iteration(k + 1, fb, fc, kb);
   } else if constexpr (PF == 2) {
-    for (; k + 1 < K; k += 2) {
-      iteration(k, fa, fb, ka);
-      iteration(k + 1, fb, fa, kb);
+    if constexpr (UNI) {
+      // uniform stores: the iterations before KST, then those after, where
+      // the compiler is told that every stage stores
+      for (; k + 1 < K && k < KST; k += 2) {
+        iteration(k, fa, fb, ka);
+        iteration(k + 1, fb, fa, kb);
+      }
+      for (; k + 1 < K; k += 2) {
+        __builtin_assume(k >= KST);
+        iteration(k, fa, fb, ka);
+        iteration(k + 1, fb, fa, kb);
+      }
+    } else {
+      for (; k + 1 < K; k += 2) {
+        iteration(k, fa, fb, ka);
+        iteration(k + 1, fb, fa, kb);
+      }
     }
     if (k < K) iteration(k, fa, fb, ka);
   } else {
@@ -1006,7 +1076,15 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
         iteration(k + 5, fa, fa, ka);
       }
     }
-    for (; k < K; ++k) iteration(k, fa, fa, ka);
+    if constexpr (UNI) {
+      for (; k < K && k < KST; ++k) iteration(k, fa, fa, ka);
+      for (; k < K; ++k) {
+        __builtin_assume(k >= KST);
+        iteration(k, fa, fa, ka);
+      }
+    } else {
+      for (; k < K; ++k) iteration(k, fa, fa, ka);
+    }
   }
 
   const unsigned long long m = __ballot(bad);
