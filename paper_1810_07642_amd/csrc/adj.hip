@@ -265,10 +265,11 @@ __device__ __forceinline__ T load_kap(const AdjArgs &A, const AdjLane<T> &L, int
   return ld_t<T>(make_rsrc((const char *)A.kfield + (size_t)row * rb, rb), L.kap);
 }
 
-// The resource of row y of the dLoss/dkappa records.
-__device__ __forceinline__ rsrc_t gk_row(const AdjArgs &A, int y) {
+// The resource of row y of the dLoss/dkappa records; with `valid` false an
+// empty range (its loads read zeros and touch no memory).
+__device__ __forceinline__ rsrc_t gk_row(const AdjArgs &A, int y, bool valid = true) {
   const uint32_t rb = (uint32_t)A.nstrips * kGkRB;
-  return make_rsrc(A.gk + (size_t)y * rb, rb);
+  return make_rsrc(A.gk + (size_t)y * rb, valid ? rb : 0u);
 }
 
 // One reverse step as a machine over the rows of a strip, one column per
@@ -456,9 +457,13 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
     mf.feed(v, unused);
   }
   load_row(ry);
-  double gkn = ld_f64(gk_row(A, y0), L.gk);  // dLoss/dkappa of the next output row
+  // dLoss/dkappa of the next output row, in two slots taken by the parity of
+  // the row in the unrolled loop (gcur: this row's entry, gnext: where the
+  // next row's goes), so that the value never moves between registers: a
+  // move would wait for the load just issued
+  double gka = ld_f64(gk_row(A, y0), L.gk), gkb = 0.0;
 
-  auto iteration = [&](int k) {
+  auto iteration = [&](int k, double &gcur, double &gnext) {
     T mu0[9];
     if constexpr (W1) {
       mf.feed(mun, mu0);
@@ -483,8 +488,12 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
         S.out(mu2, lam, gt, C);
         store_lambda(A, L, y, lam);
       }
-      double g = gkn;
-      if (k + 1 < K) gkn = ld_f64(gk_row(A, y + 1), L.gk);
+      // the next row's entry is read one row ahead, on every row (past the
+      // last an empty range): a load skipped on some path would make the
+      // compiler join its two values right after it, waiting for the load and
+      // for everything issued before it
+      double g = gcur;
+      gnext = ld_f64(gk_row(A, y + 1, k + 1 < K), L.gk);
       if (L.out) g += gt;
       st_f64(gk_row(A, y), L.gk, g);
     }
@@ -501,15 +510,17 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
   int k = 0;
   if constexpr (W1 && sizeof(T) == 4) {
     for (; k + 5 < K; k += 6) {
-      iteration(k);
-      iteration(k + 1);
-      iteration(k + 2);
-      iteration(k + 3);
-      iteration(k + 4);
-      iteration(k + 5);
+      iteration(k, gka, gkb);
+      iteration(k + 1, gkb, gka);
+      iteration(k + 2, gka, gkb);
+      iteration(k + 3, gkb, gka);
+      iteration(k + 4, gka, gkb);
+      iteration(k + 5, gkb, gka);
     }
   }
-  for (; k < K; ++k) iteration(k);
+  // one slot (the entry is copied before the next one is loaded); k is even
+  // here, so gka holds the next output row's entry
+  for (; k < K; ++k) iteration(k, gka, gka);
 }
 
 // Two reverse steps, t and t-1, in one pass.  The step-t stage runs as in
@@ -578,9 +589,11 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
   }
   load1(0, ia);
   load1(1, ib);
-  double gkn = ld_f64(gk_row(A, y0), L.gk);  // dLoss/dkappa of the next output row
+  // dLoss/dkappa of the next output row, in two slots taken by the parity of
+  // the row, as in adj_step_kernel
+  double gka = ld_f64(gk_row(A, y0), L.gk), gkb = 0.0;
 
-  auto iteration = [&](int k, AdjIn<T> &in, AdjCap<T> &cin) {
+  auto iteration = [&](int k, AdjIn<T> &in, AdjCap<T> &cin, double &gcur, double &gnext) {
     T mu0[9];
     if constexpr (W1) {
       mf.feed(in.mu, mu0);
@@ -645,8 +658,8 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
           S2.out(mo, lam, gt, C);
           store_lambda(A, L, y, lam);
         }
-        double g = gkn;
-        if (k + 1 < K) gkn = ld_f64(gk_row(A, y + 1), L.gk);
+        double g = gcur;  // the next row's entry is read on every row, as in adj_step_kernel
+        gnext = ld_f64(gk_row(A, y + 1, k + 1 < K), L.gk);
         if (L.out) {
           g += gring[(k + 1) & 3][lane];  // the step-t term of row y, from iteration k-3
           g += gt;
@@ -662,18 +675,18 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
   // 4096^2 FP32 with omega = 1 186 -> 174 us per step, 1024^2 20.0 -> 17.7
   int k = 0;
   for (; k + 5 < K; k += 6) {
-    iteration(k, ia, ca);
-    iteration(k + 1, ib, cb);
-    iteration(k + 2, ia, ca);
-    iteration(k + 3, ib, cb);
-    iteration(k + 4, ia, ca);
-    iteration(k + 5, ib, cb);
+    iteration(k, ia, ca, gka, gkb);
+    iteration(k + 1, ib, cb, gkb, gka);
+    iteration(k + 2, ia, ca, gka, gkb);
+    iteration(k + 3, ib, cb, gkb, gka);
+    iteration(k + 4, ia, ca, gka, gkb);
+    iteration(k + 5, ib, cb, gkb, gka);
   }
   for (; k + 1 < K; k += 2) {
-    iteration(k, ia, ca);
-    iteration(k + 1, ib, cb);
+    iteration(k, ia, ca, gka, gkb);
+    iteration(k + 1, ib, cb, gkb, gka);
   }
-  if (k < K) iteration(k, ia, ca);
+  if (k < K) iteration(k, ia, ca, gka, gkb);
 }
 
 // nu_l(x, y) = lambda^N_l(x, y + c_ly) = dLoss/dh_N(x, y + c_ly) for every l
