@@ -26,8 +26,8 @@ FLAGS = [
     f"--offload-arch={ARCH}",
     # keep packed FP32 instructions out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # no fused multiply-add contraction: the FP64 step stays within a few ulp
-    # of the unfused reference arithmetic
+    # no implicit fused multiply-add contraction: the kernels fuse where they
+    # say so (madd, the reciprocal refinement), nowhere else
     "-ffp-contract=off",
     "-Wall", "-Wno-unused-result",
     # per-kernel register and scratch report (checked below)

@@ -223,14 +223,30 @@ __device__ __forceinline__ double from_right(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// a * b + c: fused for FP32 (one rounding), two roundings for FP64 so that the
-// FP64 step keeps the unfused arithmetic of its reference.
+// a * b + c, fused (one rounding) in both precisions.  The FP64 step once kept
+// two roundings, as its unfused reference does; fused it is 3 % faster at
+// 4096^2 (82.3k -> 84.9k MLUPS on one box) and as close to the FP64 oracle
+// (every parity test within its 1e-12).  Nothing else is contracted
+// (-ffp-contract=off).
 __device__ __forceinline__ float madd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double madd(double a, double b, double c) { return a * b + c; }
+__device__ __forceinline__ double madd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// 1/x: the hardware reciprocal (about 1 ulp) in FP32, correctly rounded in FP64.
+// 1/x: the hardware reciprocal (about 1 ulp) in FP32; in FP64 the hardware
+// estimate refined by two Newton-Raphson steps, r <- r + r (1 - x r), each an
+// FMA pair (within about an ulp for the film heights and friction
+// denominators it serves, which are normal numbers far from the range ends).
+// The correctly rounded quotient costs about eleven instructions against five
+// (scaling, a correction step and the final fix-up); with three reciprocals
+// per site and step the FP64 step ran 4.9 % faster at 4096^2 (75.7k -> 79.4k
+// MLUPS on one box), and stays within 1e-12 of the FP64 oracle.
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
 
 // (h_*/h)^n - (h_*/h)^m given r = h_*/h; (9, 3) and (3, 9) without loops.
 template <typename T> __device__ __forceinline__ T ipow(T x, int n);
