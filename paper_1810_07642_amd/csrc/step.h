@@ -139,6 +139,29 @@ __device__ __forceinline__ void load_row(rsrc_t row, const Lane<kF32> &L, unsign
   }
 }
 
+// FP32 rows of a strip whose lanes all hold aligned column pairs: nine 64-bit
+// loads and no per-lane branch.
+__device__ __forceinline__ void load_row_vec(rsrc_t row, const Lane<kF32> &L, unsigned long long (&out)[9]) {
+#pragma unroll
+  for (int l = 0; l < 9; ++l)
+    out[l] = __builtin_bit_cast(unsigned long long,
+                                __builtin_amdgcn_raw_buffer_load_b64(row, L.oe[0] + seg_offset<kF32>(l), 0, kLoadPolicy));
+}
+
+// FP16S rows of a strip whose lanes all hold aligned column pairs: the rest
+// slot as one 64-bit load, each moving population as one 32-bit word of two
+// FP16 values (as load_raw's vector path), no per-lane branch.
+__device__ __forceinline__ void load_row_vec16(rsrc_t row, const Lane<kF16S> &L, float (&out)[9][2]) {
+  const float2 v = ld_f32x2(row, L.oe[0] + seg_offset<kF16S>(0));
+  out[0][0] = v.x;
+  out[0][1] = v.y;
+#pragma unroll
+  for (int l = 1; l < 9; ++l) {
+    out[l][0] = __uint_as_float(__builtin_bit_cast(unsigned int, ld_f16x2(row, L.o16[0] + seg_offset<kF16S>(l))));
+    out[l][1] = 0.0f;
+  }
+}
+
 // Per-site field of the film pressure (field kind KF):
 //   kNoField: none (uniform kappa0 and gamma);
 //   kKappa: kappa [ny][ldx] in T;
@@ -487,11 +510,12 @@ constexpr int kStoreDrop = 0x7fff0000;
 // pass at 4096^2 72.4k -> 77.9k, at 2048^2 63.6k -> 69.8k; the general stages
 // (two steps) at 4096^2 54.5k -> 57.9k.  Left out where it lost: the one- and
 // two-step omega = 1 kernels of small lattices, whose tiles are bound by their
-// chain of rows (256^2 10.3k -> 9.1k), and FP32 and FP16S, whose VALU fills
-// more of the wait (2 % and 5 % slower: more registers, FP16S spills); the
-// capture and surface tension kernels would spill.
+// chain of rows (256^2 10.3k -> 9.1k), and FP32 and FP16S outside the aligned
+// specialisation of their main kernels (step_kernel's row loop; with the
+// per-lane load branches of the general loop FP32 ran 2 % and FP16S 5 %
+// slower, in it 2 % and 5 % faster); the capture and surface tension kernels
+// would spill.
 template <int P> __device__ __forceinline__ void drop_row_stores(const StepArgs &A) {
-  static_assert(P == kF64, "uniform stores are built for FP64 records");
   // byte stores at distinct offsets: a store of this width occurs nowhere
   // else, so the compiler neither merges these with a row's stores nor drops
   // them as duplicates
@@ -517,12 +541,18 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
   const rsrc_t rowD[3] = {make_rsrc(A.dst + yS * rowB, (uint32_t)rowB), make_rsrc(A.dst + y * rowB, (uint32_t)rowB),
                           make_rsrc(A.dst + yN * rowB, (uint32_t)rowB)};  // indexed by c_ly + 1
   const bool pair = L.pair;
-  static_assert(!UNI || P == kF64, "uniform stores are built for FP64 records");
-  if constexpr (UNI) {
-    // nine stores and three padding stores on every path
-    const int oe = L.out[0] ? L.oe[0] : kStoreDrop;  // one column per lane: pair == out[0]
+  if constexpr (UNI && P != kF16S) {
+    // nine stores and three padding stores on every path (FP32: only where
+    // every lane stores both of its columns or none, fast_store)
+    if constexpr (P == kF64) {
+      const int oe = L.out[0] ? L.oe[0] : kStoreDrop;  // one column per lane: pair == out[0]
 #pragma unroll
-    for (int l = 0; l < 9; ++l) st_f64(rowD[kCy[l] + 1], oe + seg_offset<P>(l), post[l][0]);
+      for (int l = 0; l < 9; ++l) st_f64(rowD[kCy[l] + 1], oe + seg_offset<P>(l), post[l][0]);
+    } else {
+      const int oe = pair ? L.oe[0] : kStoreDrop;
+#pragma unroll
+      for (int l = 0; l < 9; ++l) st_f32x2(rowD[kCy[l] + 1], oe + seg_offset<P>(l), post[l][0], post[l][1]);
+    }
     const bool full = xend - x0 == B;
     const int rec = (x0 / B) * RB;
 #pragma unroll
@@ -550,7 +580,20 @@ __device__ __forceinline__ void store_row(const StepArgs &A, int y, const typena
       for (int l = 1; l < 9; ++l)
         qw[l] = enc16x2(post[l][0] - rest16_l(e0, l), post[l][1] - rest16_l(e1, l), A.qscale);
     }
-    if (L.fast_store) {
+    if constexpr (UNI) {
+      const int o16 = pair ? L.o16[0] : kStoreDrop, oe = pair ? L.oe[0] : kStoreDrop;
+#pragma unroll
+      for (int l = 1; l < 9; ++l)
+        __builtin_amdgcn_raw_buffer_store_b32(qw[l], rowD[kCy[l] + 1], o16 + seg_offset<P>(l), 0, kStorePolicy);
+      st_f32x2(rowD[1], oe, rest[0], rest[1]);
+      const bool full = xend - x0 == B;
+      const int rec = (x0 / B) * RB;
+#pragma unroll
+      for (int g = 0; g < 3; ++g)
+        st_f32(rowD[g == 0 ? 1 : (g == 1 ? 2 : 0)],
+               full && 4 * lane < pad_bytes<P>(g) ? rec + pad_offset<P>(g) + 4 * lane : kStoreDrop, 0.f);
+      return;
+    } else if (L.fast_store) {
       if (pair) {
 #pragma unroll
         for (int l = 1; l < 9; ++l)
@@ -856,7 +899,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   // uniform stores (store_row) and KST, the first row iteration whose last
   // stage stores a row (each stage emits from its fifth row on, and stage s
   // starts six rows after stage s - 1)
-  constexpr bool UNI = P == kF64 && !CAP && KF != kGammaKappa && (NS == 3 || !W1);
+  constexpr bool UNI64 = P == kF64 && !CAP && KF != kGammaKappa && (NS == 3 || !W1);
   constexpr int KST = 4 + 6 * (NS - 1);
   auto rsrc_src = [&](int row) { return make_rsrc(A.src + row * rowB, (uint32_t)rowB); };
   int ry = wrap(y0 - HALO, ny);                          // row r of stage 0
@@ -893,10 +936,32 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   constexpr int KQ = NS >= 2 ? 3 * (NS - 1) : 1;
   T kq[KQ][V], aq[KQ][V];
   using RowBuf = std::conditional_t<P == kF32, unsigned long long[9], T[9][V]>;
+  // The row loop.  The FP32 kernel with three omega = 1 steps and the FP16S
+  // kernel with two (at g = 0) are specialised for strips whose lanes all hold
+  // aligned column pairs and store both or neither of their columns (AV, every
+  // strip of a lattice whose width is a multiple of the record): their row
+  // loads then have no per-lane branch (the compiler had merged the two load
+  // shapes into masked branches per population) and they take the uniform
+  // stores (store_row) that FP64 takes.  Bitwise the same results; at 4096^2
+  // FP32 154.2k -> 157.5k MLUPS (the specialisation alone gained nothing, the
+  // uniform stores 2 %), FP16S 164.5k -> 172.3k.  The other kernels of the two
+  // forms would spill with it.
+  constexpr bool AV_SPEC = (P == kF32 && W1 && NS == 3 && !CAP && KF != kGammaKappa) ||
+                        (P == kF16S && G0 && W1 && NS == 2 && !CAP && KF != kGammaKappa);
+  auto run = [&](auto av) {
+  constexpr bool AV = decltype(av)::value;
+  constexpr bool UNI = UNI64 || AV;
   RowBuf fa, fb, fc;  // stored values of rows r (being consumed), r + 1 and r + 2
   auto load_buf = [&](rsrc_t row, RowBuf &out) {
-    if constexpr (P == kF32) load_row(row, L, out);
-    else load_row<P>(row, L, out, A);
+    if constexpr (P == kF32) {
+      if constexpr (AV) load_row_vec(row, L, out);
+      else load_row(row, L, out);
+    } else if constexpr (P == kF16S) {
+      if constexpr (AV) load_row_vec16(row, L, out);
+      else load_row<P>(row, L, out, A);
+    } else {
+      load_row<P>(row, L, out, A);
+    }
   };
   load_buf(rsrc_src(ry), fa);
   if constexpr (KF != kNoField) load_kappa<P, KF>(rsrc_kap(ry), L, ka);
@@ -1019,7 +1084,30 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   // rows in groups of PF, so that each buffer keeps its registers around the
   // loop; the last rows after it
   int k = 0;
-  if constexpr (PF == 3) {
+  if constexpr (PF == 3 && UNI) {
+    for (; k + 2 < K && k < KST; k += 3) {
+      iteration(k, fa, fb, ka);
+      iteration(k + 1, fb, fc, kb);
+      iteration(k + 2, fc, fa, kc);
+    }
+    for (; k + 5 < K; k += 6) {
+      __builtin_assume(k >= KST);
+      iteration(k, fa, fb, ka);
+      iteration(k + 1, fb, fc, kb);
+      iteration(k + 2, fc, fa, kc);
+      iteration(k + 3, fa, fb, ka);
+      iteration(k + 4, fb, fc, kb);
+      iteration(k + 5, fc, fa, kc);
+    }
+    for (; k + 2 < K; k += 3) {
+      __builtin_assume(k >= KST);
+      iteration(k, fa, fb, ka);
+      iteration(k + 1, fb, fc, kb);
+      iteration(k + 2, fc, fa, kc);
+    }
+    if (k < K) iteration(k, fa, fb, ka);
+    if (k + 1 < K) iteration(k + 1, fb, fc, kb);
+  } else if constexpr (PF == 3) {
     // FP16S: groups of six rows (two turns of the three buffers and a whole
     // number of turns of every row history: fewer register moves; +4 % at
     // 4096^2, the form bound by its VALU), then of three.  Not with a
@@ -1066,25 +1154,34 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
     // so that the stages' row histories keep their registers (a third fewer
     // moves, +1 %); FP64, the general stages and the surface tension field
     // would need more than 256 VGPRs unrolled
-    if constexpr (P == kF32 && W1 && KF != kGammaKappa) {
-      for (; k + 5 < K; k += 6) {
-        iteration(k, fa, fa, ka);
-        iteration(k + 1, fa, fa, ka);
-        iteration(k + 2, fa, fa, ka);
-        iteration(k + 3, fa, fa, ka);
-        iteration(k + 4, fa, fa, ka);
-        iteration(k + 5, fa, fa, ka);
-      }
-    }
     if constexpr (UNI) {
+      // (FP32 without the groups of six of the other branch: with the
+      // uniform stores they would spill)
       for (; k < K && k < KST; ++k) iteration(k, fa, fa, ka);
       for (; k < K; ++k) {
         __builtin_assume(k >= KST);
         iteration(k, fa, fa, ka);
       }
     } else {
+      if constexpr (P == kF32 && W1 && KF != kGammaKappa) {
+        for (; k + 5 < K; k += 6) {
+          iteration(k, fa, fa, ka);
+          iteration(k + 1, fa, fa, ka);
+          iteration(k + 2, fa, fa, ka);
+          iteration(k + 3, fa, fa, ka);
+          iteration(k + 4, fa, fa, ka);
+          iteration(k + 5, fa, fa, ka);
+        }
+      }
       for (; k < K; ++k) iteration(k, fa, fa, ka);
     }
+  }
+  };
+  if constexpr (AV_SPEC) {
+    if (L.allvec && L.fast_store) run(std::true_type{});
+    else run(std::false_type{});
+  } else {
+    run(std::false_type{});
   }
 
   const unsigned long long m = __ballot(bad);
