@@ -746,16 +746,27 @@ __device__ __forceinline__ void fp16s_decode(const float (&cur)[9][V], const flo
 
 // Moments (h, jx, jy) of row q of the pre-collision state of one step, for
 // the reverse sweep, into the capture records at `base` (cap_record_bytes).
-template <int P>
+// UNI (the aligned FP32 copy of the row loop, where every lane stores both of
+// its columns or neither): the same four stores on every path, lanes without
+// output and rows outside the tile (`valid` false: an empty range) dropped.
+template <int P, bool UNI = false>
 __device__ __forceinline__ void capture_row(const StepArgs &A, char *base, int q, const typename Form<P>::T (&hv)[Form<P>::V],
                                             const typename Form<P>::T (&jxv)[Form<P>::V],
                                             const typename Form<P>::T (&jyv)[Form<P>::V], const Lane<P> &L,
-                                            typename Form<P>::T href, int x0, int xend, int lane) {
+                                            typename Form<P>::T href, int x0, int xend, int lane, bool valid = true) {
   using T = typename Form<P>::T;
   constexpr int V = Form<P>::V, B = Form<P>::B, ES = sizeof(T);
   constexpr int CRB = cap_record_bytes<P>(), SEG = B * ES;
   const uint32_t rowb = (uint32_t)(A.nblk * CRB);
-  const rsrc_t row = make_rsrc(base + (size_t)q * rowb, rowb);
+  const rsrc_t row = make_rsrc(base + (size_t)(valid ? q : 0) * rowb, valid ? rowb : 0u);
+  if constexpr (UNI && V == 2) {
+    const int oc = L.pair ? L.oc[0] : kStoreDrop;
+    st_f32x2(row, oc, href + hv[0], href + hv[1]);
+    st_f32x2(row, oc + SEG, jxv[0], jxv[1]);
+    st_f32x2(row, oc + 2 * SEG, jyv[0], jyv[1]);
+    st_f32(row, xend - x0 == B && 4 * lane < CRB - 3 * SEG ? (x0 / B) * CRB + 3 * SEG + 4 * lane : kStoreDrop, 0.f);
+    return;
+  }
   if constexpr (V == 2) {
     if (L.pair) {
       st_f32x2(row, L.oc[0], href + hv[0], href + hv[1]);
@@ -936,17 +947,19 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   constexpr int KQ = NS >= 2 ? 3 * (NS - 1) : 1;
   T kq[KQ][V], aq[KQ][V];
   using RowBuf = std::conditional_t<P == kF32, unsigned long long[9], T[9][V]>;
-  // The row loop.  The FP32 kernel with three omega = 1 steps and the FP16S
-  // kernel with two (at g = 0) are specialised for strips whose lanes all hold
+  // The row loop.  The FP32 kernels with three omega = 1 steps (with and
+  // without captures) and the FP16S kernel with two (at g = 0) are specialised
+  // for strips whose lanes all hold
   // aligned column pairs and store both or neither of their columns (AV, every
   // strip of a lattice whose width is a multiple of the record): their row
   // loads then have no per-lane branch (the compiler had merged the two load
   // shapes into masked branches per population) and they take the uniform
   // stores (store_row) that FP64 takes.  Bitwise the same results; at 4096^2
   // FP32 154.2k -> 157.5k MLUPS (the specialisation alone gained nothing, the
-  // uniform stores 2 %), FP16S 164.5k -> 172.3k.  The other kernels of the two
-  // forms would spill with it.
-  constexpr bool AV_SPEC = (P == kF32 && W1 && NS == 3 && !CAP && KF != kGammaKappa) ||
+  // uniform stores 2 %), FP16S 164.5k -> 172.3k, the FP32 recompute with
+  // captures 156.1 -> 151.6 us per step (its captures uniform too,
+  // capture_row).  The other kernels of the two forms would spill with it.
+  constexpr bool AV_SPEC = (P == kF32 && W1 && NS == 3 && KF != kGammaKappa) ||
                         (P == kF16S && G0 && W1 && NS == 2 && !CAP && KF != kGammaKappa);
   auto run = [&](auto av) {
   constexpr bool AV = decltype(av)::value;
@@ -1024,7 +1037,8 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
       } else {
         const int e = k - 4;  // emission index of stage 0
         if constexpr (CAP) {
-          if (q >= y0 && q < yend) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane);
+          if constexpr (UNI) capture_row<P, true>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane, q >= y0 && q < yend);
+          else if (q >= y0 && q < yend) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane);
         }
         if constexpr (P == kF16S) fp16s_roundtrip<V, G0>(post, hv, A);  // as if stored and reloaded
         T g[9][V];
@@ -1042,7 +1056,9 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
             } else {
               const int e1 = j - 4;  // emission index of stage 1
               if constexpr (CAP) {
-                if (q1 >= y0 && q1 < yend)
+                if constexpr (UNI)
+                  capture_row<P, true>(A, A.capture + capblk, q1, hv2, jx2, jy2, L, C.href, x0, xend, lane, q1 >= y0 && q1 < yend);
+                else if (q1 >= y0 && q1 < yend)
                   capture_row<P>(A, A.capture + capblk, q1, hv2, jx2, jy2, L, C.href, x0, xend, lane);
               }
               if constexpr (P == kF16S) fp16s_roundtrip<V, G0>(post2, hv2, A);
@@ -1057,7 +1073,7 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
                   const int q2 = y0 - HALO + 4 + j2;
                   store_row<P, G0, UNI>(A, q2, post3, hv3, L, x0, xend, lane);
                   if constexpr (CAP)
-                    capture_row<P>(A, A.capture + 2 * capblk, q2, hv3, jx3, jy3, L, C.href, x0, xend, lane);
+                    capture_row<P, UNI>(A, A.capture + 2 * capblk, q2, hv3, jx3, jy3, L, C.href, x0, xend, lane);
                 }
               }
             }
