@@ -962,174 +962,152 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   constexpr bool AV_SPEC = (P == kF32 && W1 && NS == 3 && KF != kGammaKappa) ||
                         (P == kF16S && G0 && W1 && NS == 2 && !CAP && KF != kGammaKappa);
   auto run = [&](auto av) {
-  constexpr bool AV = decltype(av)::value;
-  constexpr bool UNI = UNI64 || AV;
-  RowBuf fa, fb, fc;  // stored values of rows r (being consumed), r + 1 and r + 2
-  auto load_buf = [&](rsrc_t row, RowBuf &out) {
-    if constexpr (P == kF32) {
-      if constexpr (AV) load_row_vec(row, L, out);
-      else load_row(row, L, out);
-    } else if constexpr (P == kF16S) {
-      if constexpr (AV) load_row_vec16(row, L, out);
-      else load_row<P>(row, L, out, A);
-    } else {
-      load_row<P>(row, L, out, A);
-    }
-  };
-  load_buf(rsrc_src(ry), fa);
-  if constexpr (KF != kNoField) load_kappa<P, KF>(rsrc_kap(ry), L, ka);
-  if (PF >= 2 && KL > 1) {
-    const int r1 = (ry + 1) % ny;
-    load_buf(rsrc_src(r1), fb);
-    if constexpr (KF != kNoField) load_kappa<P, KF>(rsrc_kap(r1), L, kb);
-  }
-  if (PF == 3 && KL > 2) {
-    const int r2 = (ry + 2) % ny;
-    load_buf(rsrc_src(r2), fc);
-    if constexpr (KF != kNoField) load_kappa<P, KF>(rsrc_kap(r2), L, kc);
-  }
-  if constexpr (UNI) drop_row_stores<P>(A);  // as a row iteration leaves behind its loads
-  if constexpr (P == kF16S) {
-    // the c_ly = +1 values of the first row, which fp16s_decode otherwise
-    // carries over from the row before
-#pragma unroll
-    for (int v = 0; v < V; ++v)
-#pragma unroll
-      for (int i = 0; i < 3; ++i) cn[i][v] = unpack16(fa[2 + i][0], v, A.qinv);
-  }
-
-  auto iteration = [&](int k, RowBuf &cur, const RowBuf &nxt, KapBuf<P, KF> &kcur) {
-    T f[9][V], f2[9][V];
-    if constexpr (P == kF32) {
-#pragma unroll
-      for (int l = 0; l < 9; ++l) {
-        const u32x2 w = __builtin_bit_cast(u32x2, cur[l]);
-        const T c[2] = {__uint_as_float(w.x), __uint_as_float(w.y)};
-        shift_x<T, V>(l, c, f[l]);
-      }
-    } else if constexpr (P == kF16S) {
-      T d[9][V];
-      fp16s_decode<V, G0>(cur, nxt, cs, cq, cn, A, d);
-#pragma unroll
-      for (int l = 0; l < 9; ++l) shift_x<T, V>(l, d[l], f[l]);
-    } else {
-#pragma unroll
-      for (int l = 0; l < 9; ++l) shift_x<T, V>(l, cur[l], f[l]);
-    }
-    T k0[V], a0[V];
-    if constexpr (KF != kNoField) kappa_cols<P, KF>(kcur, k0, a0);
-    S0.ingest(k, f, k0, a0, f2, lane);
-    // prefetch row r + PF into the registers just freed.  Past the tile's last
-    // row the loads go to an empty buffer range (no memory access, zeros):
-    // every iteration issues the same loads, so the compiler's waits for a
-    // row need not drain the loads of the rows after it.
-    load_buf(k + PF < KL ? rsrc_src(rpre) : make_rsrc(A.src, 0), cur);
-    if constexpr (KF != kNoField) load_kappa<P, KF>(k + PF < KL ? rsrc_kap(rpre) : make_rsrc(A.kfield, 0), L, kcur);
-    if constexpr (UNI) {
-      if (k < KST) drop_row_stores<P>(A);
-    }
-    T post[9][V], hv[V], jxv[V], jyv[V];
-    if (S0.finish(k, f2, post, hv, jxv, jyv, C, L, bad)) {
-      const int q = y0 - HALO + k - 2;  // row of the post-collision values (unwrapped)
-      if constexpr (NS == 1) {
-        store_row<P, G0, UNI>(A, q, post, hv, L, x0, xend, lane);
-        if constexpr (CAP) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane);
+    constexpr bool AV = decltype(av)::value;
+    constexpr bool UNI = UNI64 || AV;
+    RowBuf fa, fb, fc;  // stored values of rows r (being consumed), r + 1 and r + 2
+    auto load_buf = [&](rsrc_t row, RowBuf &out) {
+      if constexpr (P == kF32) {
+        if constexpr (AV) load_row_vec(row, L, out);
+        else load_row(row, L, out);
+      } else if constexpr (P == kF16S) {
+        if constexpr (AV) load_row_vec16(row, L, out);
+        else load_row<P>(row, L, out, A);
       } else {
-        const int e = k - 4;  // emission index of stage 0
-        if constexpr (CAP) {
-          if constexpr (UNI) capture_row<P, true>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane, q >= y0 && q < yend);
-          else if (q >= y0 && q < yend) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane);
+        load_row<P>(row, L, out, A);
+      }
+    };
+    load_buf(rsrc_src(ry), fa);
+    if constexpr (KF != kNoField) load_kappa<P, KF>(rsrc_kap(ry), L, ka);
+    if (PF >= 2 && KL > 1) {
+      const int r1 = (ry + 1) % ny;
+      load_buf(rsrc_src(r1), fb);
+      if constexpr (KF != kNoField) load_kappa<P, KF>(rsrc_kap(r1), L, kb);
+    }
+    if (PF == 3 && KL > 2) {
+      const int r2 = (ry + 2) % ny;
+      load_buf(rsrc_src(r2), fc);
+      if constexpr (KF != kNoField) load_kappa<P, KF>(rsrc_kap(r2), L, kc);
+    }
+    if constexpr (UNI) drop_row_stores<P>(A);  // as a row iteration leaves behind its loads
+    if constexpr (P == kF16S) {
+      // the c_ly = +1 values of the first row, which fp16s_decode otherwise
+      // carries over from the row before
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) cn[i][v] = unpack16(fa[2 + i][0], v, A.qinv);
+    }
+
+    auto iteration = [&](int k, RowBuf &cur, const RowBuf &nxt, KapBuf<P, KF> &kcur) {
+      T f[9][V], f2[9][V];
+      if constexpr (P == kF32) {
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+          const u32x2 w = __builtin_bit_cast(u32x2, cur[l]);
+          const T c[2] = {__uint_as_float(w.x), __uint_as_float(w.y)};
+          shift_x<T, V>(l, c, f[l]);
         }
-        if constexpr (P == kF16S) fp16s_roundtrip<V, G0>(post, hv, A);  // as if stored and reloaded
-        T g[9][V];
-        H1.feed(post, g);  // row q - 1 of the next step
-        if (e >= 2) {
-          const int j = e - 2;  // stage 1 row index; its row is q - 1 = y0 - HALO + 3 + j
-          T g2[9][V];
-          S1.ingest(j, g, kq[2], aq[2], g2, lane);
-          T post2[9][V], hv2[V], jx2[V], jy2[V];
-          if (S1.finish(j, g2, post2, hv2, jx2, jy2, C, L, bad)) {
-            const int q1 = y0 - HALO + 1 + j;  // row of stage 1's post-collision values
-            if constexpr (NS == 2) {
-              store_row<P, G0, UNI>(A, q1, post2, hv2, L, x0, xend, lane);
-              if constexpr (CAP) capture_row<P>(A, A.capture + capblk, q1, hv2, jx2, jy2, L, C.href, x0, xend, lane);
-            } else {
-              const int e1 = j - 4;  // emission index of stage 1
-              if constexpr (CAP) {
-                if constexpr (UNI)
-                  capture_row<P, true>(A, A.capture + capblk, q1, hv2, jx2, jy2, L, C.href, x0, xend, lane, q1 >= y0 && q1 < yend);
-                else if (q1 >= y0 && q1 < yend)
-                  capture_row<P>(A, A.capture + capblk, q1, hv2, jx2, jy2, L, C.href, x0, xend, lane);
-              }
-              if constexpr (P == kF16S) fp16s_roundtrip<V, G0>(post2, hv2, A);
-              T g3[9][V];
-              H2.feed(post2, g3);  // row q1 - 1 of the step after
-              if (e1 >= 2) {
-                const int j2 = e1 - 2;  // stage 2 row index; its row is y0 - HALO + 6 + j2
-                T g4[9][V];
-                S2.ingest(j2, g3, kq[KQ - 1], aq[KQ - 1], g4, lane);
-                T post3[9][V], hv3[V], jx3[V], jy3[V];
-                if (S2.finish(j2, g4, post3, hv3, jx3, jy3, C, L, bad)) {
-                  const int q2 = y0 - HALO + 4 + j2;
-                  store_row<P, G0, UNI>(A, q2, post3, hv3, L, x0, xend, lane);
-                  if constexpr (CAP)
-                    capture_row<P, UNI>(A, A.capture + 2 * capblk, q2, hv3, jx3, jy3, L, C.href, x0, xend, lane);
+      } else if constexpr (P == kF16S) {
+        T d[9][V];
+        fp16s_decode<V, G0>(cur, nxt, cs, cq, cn, A, d);
+#pragma unroll
+        for (int l = 0; l < 9; ++l) shift_x<T, V>(l, d[l], f[l]);
+      } else {
+#pragma unroll
+        for (int l = 0; l < 9; ++l) shift_x<T, V>(l, cur[l], f[l]);
+      }
+      T k0[V], a0[V];
+      if constexpr (KF != kNoField) kappa_cols<P, KF>(kcur, k0, a0);
+      S0.ingest(k, f, k0, a0, f2, lane);
+      // prefetch row r + PF into the registers just freed.  Past the tile's last
+      // row the loads go to an empty buffer range (no memory access, zeros):
+      // every iteration issues the same loads, so the compiler's waits for a
+      // row need not drain the loads of the rows after it.
+      load_buf(k + PF < KL ? rsrc_src(rpre) : make_rsrc(A.src, 0), cur);
+      if constexpr (KF != kNoField) load_kappa<P, KF>(k + PF < KL ? rsrc_kap(rpre) : make_rsrc(A.kfield, 0), L, kcur);
+      if constexpr (UNI) {
+        if (k < KST) drop_row_stores<P>(A);
+      }
+      T post[9][V], hv[V], jxv[V], jyv[V];
+      if (S0.finish(k, f2, post, hv, jxv, jyv, C, L, bad)) {
+        const int q = y0 - HALO + k - 2;  // row of the post-collision values (unwrapped)
+        if constexpr (NS == 1) {
+          store_row<P, G0, UNI>(A, q, post, hv, L, x0, xend, lane);
+          if constexpr (CAP) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane);
+        } else {
+          const int e = k - 4;  // emission index of stage 0
+          if constexpr (CAP) {
+            if constexpr (UNI) capture_row<P, true>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane, q >= y0 && q < yend);
+            else if (q >= y0 && q < yend) capture_row<P>(A, A.capture, q, hv, jxv, jyv, L, C.href, x0, xend, lane);
+          }
+          if constexpr (P == kF16S) fp16s_roundtrip<V, G0>(post, hv, A);  // as if stored and reloaded
+          T g[9][V];
+          H1.feed(post, g);  // row q - 1 of the next step
+          if (e >= 2) {
+            const int j = e - 2;  // stage 1 row index; its row is q - 1 = y0 - HALO + 3 + j
+            T g2[9][V];
+            S1.ingest(j, g, kq[2], aq[2], g2, lane);
+            T post2[9][V], hv2[V], jx2[V], jy2[V];
+            if (S1.finish(j, g2, post2, hv2, jx2, jy2, C, L, bad)) {
+              const int q1 = y0 - HALO + 1 + j;  // row of stage 1's post-collision values
+              if constexpr (NS == 2) {
+                store_row<P, G0, UNI>(A, q1, post2, hv2, L, x0, xend, lane);
+                if constexpr (CAP) capture_row<P>(A, A.capture + capblk, q1, hv2, jx2, jy2, L, C.href, x0, xend, lane);
+              } else {
+                const int e1 = j - 4;  // emission index of stage 1
+                if constexpr (CAP) {
+                  if constexpr (UNI)
+                    capture_row<P, true>(A, A.capture + capblk, q1, hv2, jx2, jy2, L, C.href, x0, xend, lane, q1 >= y0 && q1 < yend);
+                  else if (q1 >= y0 && q1 < yend)
+                    capture_row<P>(A, A.capture + capblk, q1, hv2, jx2, jy2, L, C.href, x0, xend, lane);
+                }
+                if constexpr (P == kF16S) fp16s_roundtrip<V, G0>(post2, hv2, A);
+                T g3[9][V];
+                H2.feed(post2, g3);  // row q1 - 1 of the step after
+                if (e1 >= 2) {
+                  const int j2 = e1 - 2;  // stage 2 row index; its row is y0 - HALO + 6 + j2
+                  T g4[9][V];
+                  S2.ingest(j2, g3, kq[KQ - 1], aq[KQ - 1], g4, lane);
+                  T post3[9][V], hv3[V], jx3[V], jy3[V];
+                  if (S2.finish(j2, g4, post3, hv3, jx3, jy3, C, L, bad)) {
+                    const int q2 = y0 - HALO + 4 + j2;
+                    store_row<P, G0, UNI>(A, q2, post3, hv3, L, x0, xend, lane);
+                    if constexpr (CAP)
+                      capture_row<P, UNI>(A, A.capture + 2 * capblk, q2, hv3, jx3, jy3, L, C.href, x0, xend, lane);
+                  }
                 }
               }
             }
           }
         }
       }
-    }
-    if constexpr (KF != kNoField && NS >= 2) {
+      if constexpr (KF != kNoField && NS >= 2) {
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
+        for (int v = 0; v < V; ++v) {
 #pragma unroll
-        for (int i = KQ - 1; i > 0; --i) {
-          kq[i][v] = kq[i - 1][v];
-          if constexpr (KF == kGammaKappa) aq[i][v] = aq[i - 1][v];
+          for (int i = KQ - 1; i > 0; --i) {
+            kq[i][v] = kq[i - 1][v];
+            if constexpr (KF == kGammaKappa) aq[i][v] = aq[i - 1][v];
+          }
+          kq[0][v] = k0[v];
+          if constexpr (KF == kGammaKappa) aq[0][v] = a0[v];
         }
-        kq[0][v] = k0[v];
-        if constexpr (KF == kGammaKappa) aq[0][v] = a0[v];
       }
-    }
-    ry = ry + 1 == ny ? 0 : ry + 1;
-    rpre = rpre + 1 == ny ? 0 : rpre + 1;
-  };
+      ry = ry + 1 == ny ? 0 : ry + 1;
+      rpre = rpre + 1 == ny ? 0 : rpre + 1;
+    };
 
-  // rows in groups of PF, so that each buffer keeps its registers around the
-  // loop; the last rows after it
-  int k = 0;
-  if constexpr (PF == 3 && UNI) {
-    for (; k + 2 < K && k < KST; k += 3) {
-      iteration(k, fa, fb, ka);
-      iteration(k + 1, fb, fc, kb);
-      iteration(k + 2, fc, fa, kc);
-    }
-    for (; k + 5 < K; k += 6) {
-      __builtin_assume(k >= KST);
-      iteration(k, fa, fb, ka);
-      iteration(k + 1, fb, fc, kb);
-      iteration(k + 2, fc, fa, kc);
-      iteration(k + 3, fa, fb, ka);
-      iteration(k + 4, fb, fc, kb);
-      iteration(k + 5, fc, fa, kc);
-    }
-    for (; k + 2 < K; k += 3) {
-      __builtin_assume(k >= KST);
-      iteration(k, fa, fb, ka);
-      iteration(k + 1, fb, fc, kb);
-      iteration(k + 2, fc, fa, kc);
-    }
-    if (k < K) iteration(k, fa, fb, ka);
-    if (k + 1 < K) iteration(k + 1, fb, fc, kb);
-  } else if constexpr (PF == 3) {
-    // FP16S: groups of six rows (two turns of the three buffers and a whole
-    // number of turns of every row history: fewer register moves; +4 % at
-    // 4096^2, the form bound by its VALU), then of three.  Not with a
-    // surface tension field and captures, where six would spill.
-    if constexpr (!(KF == kGammaKappa && CAP)) {
+    // rows in groups of PF, so that each buffer keeps its registers around the
+    // loop; the last rows after it
+    int k = 0;
+    if constexpr (PF == 3 && UNI) {
+      for (; k + 2 < K && k < KST; k += 3) {
+        iteration(k, fa, fb, ka);
+        iteration(k + 1, fb, fc, kb);
+        iteration(k + 2, fc, fa, kc);
+      }
       for (; k + 5 < K; k += 6) {
+        __builtin_assume(k >= KST);
         iteration(k, fa, fb, ka);
         iteration(k + 1, fb, fc, kb);
         iteration(k + 2, fc, fa, kc);
@@ -1137,61 +1115,83 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
         iteration(k + 4, fb, fc, kb);
         iteration(k + 5, fc, fa, kc);
       }
-    }
-    for (; k + 2 < K; k += 3) {
-      iteration(k, fa, fb, ka);
-      iteration(k + 1, fb, fc, kb);
-      iteration(k + 2, fc, fa, kc);
-    }
-    if (k < K) iteration(k, fa, fb, ka);
-    if (k + 1 < K) iteration(k + 1, fb, fc, kb);
-  } else if constexpr (PF == 2) {
-    if constexpr (UNI) {
-      // uniform stores: the iterations before KST, then those after, where
-      // the compiler is told that every stage stores
-      for (; k + 1 < K && k < KST; k += 2) {
-        iteration(k, fa, fb, ka);
-        iteration(k + 1, fb, fa, kb);
-      }
-      for (; k + 1 < K; k += 2) {
+      for (; k + 2 < K; k += 3) {
         __builtin_assume(k >= KST);
         iteration(k, fa, fb, ka);
-        iteration(k + 1, fb, fa, kb);
+        iteration(k + 1, fb, fc, kb);
+        iteration(k + 2, fc, fa, kc);
       }
-    } else {
-      for (; k + 1 < K; k += 2) {
-        iteration(k, fa, fb, ka);
-        iteration(k + 1, fb, fa, kb);
-      }
-    }
-    if (k < K) iteration(k, fa, fb, ka);
-  } else {
-    // one row ahead (three steps): FP32 with omega = 1 in groups of six rows,
-    // so that the stages' row histories keep their registers (a third fewer
-    // moves, +1 %); FP64, the general stages and the surface tension field
-    // would need more than 256 VGPRs unrolled
-    if constexpr (UNI) {
-      // (FP32 without the groups of six of the other branch: with the
-      // uniform stores they would spill)
-      for (; k < K && k < KST; ++k) iteration(k, fa, fa, ka);
-      for (; k < K; ++k) {
-        __builtin_assume(k >= KST);
-        iteration(k, fa, fa, ka);
-      }
-    } else {
-      if constexpr (P == kF32 && W1 && KF != kGammaKappa) {
+      if (k < K) iteration(k, fa, fb, ka);
+      if (k + 1 < K) iteration(k + 1, fb, fc, kb);
+    } else if constexpr (PF == 3) {
+      // FP16S: groups of six rows (two turns of the three buffers and a whole
+      // number of turns of every row history: fewer register moves; +4 % at
+      // 4096^2, the form bound by its VALU), then of three.  Not with a
+      // surface tension field and captures, where six would spill.
+      if constexpr (!(KF == kGammaKappa && CAP)) {
         for (; k + 5 < K; k += 6) {
-          iteration(k, fa, fa, ka);
-          iteration(k + 1, fa, fa, ka);
-          iteration(k + 2, fa, fa, ka);
-          iteration(k + 3, fa, fa, ka);
-          iteration(k + 4, fa, fa, ka);
-          iteration(k + 5, fa, fa, ka);
+          iteration(k, fa, fb, ka);
+          iteration(k + 1, fb, fc, kb);
+          iteration(k + 2, fc, fa, kc);
+          iteration(k + 3, fa, fb, ka);
+          iteration(k + 4, fb, fc, kb);
+          iteration(k + 5, fc, fa, kc);
         }
       }
-      for (; k < K; ++k) iteration(k, fa, fa, ka);
+      for (; k + 2 < K; k += 3) {
+        iteration(k, fa, fb, ka);
+        iteration(k + 1, fb, fc, kb);
+        iteration(k + 2, fc, fa, kc);
+      }
+      if (k < K) iteration(k, fa, fb, ka);
+      if (k + 1 < K) iteration(k + 1, fb, fc, kb);
+    } else if constexpr (PF == 2) {
+      if constexpr (UNI) {
+        // uniform stores: the iterations before KST, then those after, where
+        // the compiler is told that every stage stores
+        for (; k + 1 < K && k < KST; k += 2) {
+          iteration(k, fa, fb, ka);
+          iteration(k + 1, fb, fa, kb);
+        }
+        for (; k + 1 < K; k += 2) {
+          __builtin_assume(k >= KST);
+          iteration(k, fa, fb, ka);
+          iteration(k + 1, fb, fa, kb);
+        }
+      } else {
+        for (; k + 1 < K; k += 2) {
+          iteration(k, fa, fb, ka);
+          iteration(k + 1, fb, fa, kb);
+        }
+      }
+      if (k < K) iteration(k, fa, fb, ka);
+    } else {
+      // one row ahead (three steps): FP32 with omega = 1 in groups of six rows,
+      // so that the stages' row histories keep their registers (a third fewer
+      // moves, +1 %); FP64, the general stages and the surface tension field
+      // would need more than 256 VGPRs unrolled
+      if constexpr (UNI) {
+        // (FP32 without the groups of six of the other branch: with the
+        // uniform stores they would spill)
+        for (; k < K && k < KST; ++k) iteration(k, fa, fa, ka);
+        for (; k < K; ++k) {
+          __builtin_assume(k >= KST);
+          iteration(k, fa, fa, ka);
+        }
+      } else {
+        if constexpr (P == kF32 && W1 && KF != kGammaKappa) {
+          for (; k + 5 < K; k += 6) {
+            iteration(k, fa, fa, ka);
+            iteration(k + 1, fa, fa, ka);
+            iteration(k + 2, fa, fa, ka);
+            iteration(k + 3, fa, fa, ka);
+            iteration(k + 4, fa, fa, ka);
+            iteration(k + 5, fa, fa, ka);
+          }
+        }
+        for (; k < K; ++k) iteration(k, fa, fa, ka);
+      }
     }
-  }
   };
   if constexpr (AV_SPEC) {
     if (L.allvec && L.fast_store) run(std::true_type{});
