@@ -266,13 +266,15 @@ def inverse_design_case(prec="fp32", n=512, steps=4096, K=64, reps=2):
     return info, (h0c.grad.detach(), thc.grad.detach())
 
 
-def reverse_sweep_at(n, ceiling_gbs, K=16):
+def reverse_sweep_at(n, ceiling_gbs, K=18):
     """Per-step times of the pieces of the backward pass at n x n (the dewetting
     recipe, FP32): forward step, recompute with capture, and the adjoint, both
     two steps per pass (tflbm_adj_steps, what the backward pass runs) and one
     step per pass (tflbm_adj_step); the backward/forward ratio they give
     (checkpoint copies excluded), and the roofline block of the two-step
-    reverse kernel (68 B per site and pass at tau = 1)."""
+    reverse kernel (68 B per site and pass at tau = 1).  K = 18 steps are whole
+    passes of each piece (six of three forward or recompute steps, nine of two
+    reverse steps), so every piece is timed at its steady per-step rate."""
     import ctypes
     import torch
     from paper_1810_07642_amd import Sim, inputs
