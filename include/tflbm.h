@@ -84,7 +84,10 @@ enum {
 enum { TFLBM_FP64 = 0, TFLBM_FP32 = 1, TFLBM_FP16S = 2 };
 
 typedef struct tflbm_params {
-  int32_t nx, ny;          /* periodic lattice size, >= 1 each, ny * roundup(nx, 64) < 2^31, one row of records < 2 GiB */
+  int32_t nx, ny;          /* periodic lattice size, >= 1 each, ny * roundup(nx, 64) < 2^31, and every row of
+                              population, capture and adjoint records < 0x7fff0000 bytes (the kernels aim the
+                              stores they drop past it): nx up to about 28.5 million in FP64, 53 million in
+                              FP32 and FP16S */
   int32_t prec;            /* TFLBM_FP64, TFLBM_FP32 or TFLBM_FP16S */
   int32_t n_exp, m_exp;    /* disjoining exponents n != m, 1..32 (paper: 9 and 3) */
   int32_t fp16_scale_log2; /* TFLBM_FP16S scale exponent s, 0..24 */

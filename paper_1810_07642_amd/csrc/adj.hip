@@ -22,6 +22,7 @@
 // and stores lambda^t_l(x) for step t-1 (layout: AdjRec).
 // The forward moments h, j of step t come from the capture written by the
 // forward step; the film pressure and its gradient are recomputed from h.
+#include <algorithm>
 #include <cstring>
 
 #include "device.h"
@@ -44,7 +45,7 @@ namespace tflbm {
 constexpr int kAdjW = 54;     // columns per strip and record
 constexpr int kAdjHalo = 5;   // halo columns per side: two per reverse step and the shift between two steps
 constexpr int kGkRB = 64 * 8;  // bytes of a dLoss/dkappa record
-constexpr int kDropOffset = 0x7fff0000;  // a buffer offset past every row: the access is dropped
+constexpr int kDropOffset = kDropBytes;  // a buffer offset past every row: the access is dropped
 static_assert(kAdjW + 2 * kAdjHalo == 64, "a strip and its halo fill one wavefront");
 template <typename T> struct AdjRec {
   static constexpr int SEG = kAdjW * (int)sizeof(T);
@@ -82,6 +83,11 @@ struct AdjArgs {
 };
 
 int adj_record_columns() { return kAdjW; }
+int adj_record_bytes_max(int prec) {
+  const int a = prec == kF64 ? std::max(AdjRec<double>::RB, AdjRec1<double>::RB)
+                             : std::max(AdjRec<float>::RB, AdjRec1<float>::RB);
+  return std::max(a, kGkRB);
+}
 
 // Lambda_F = 3 sum_l w_l c_l mu_l through differences of opposite populations.
 template <typename T>

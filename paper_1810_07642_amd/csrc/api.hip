@@ -247,9 +247,14 @@ int tflbm_check_params(const tflbm_params *p) {
   const int64_t ldx = ((int64_t)p->nx + 63) / 64 * 64;
   if ((int64_t)p->ny * ldx >= ((int64_t)1 << 31)) return TFLBM_EINVAL;
   if (p->prec < TFLBM_FP64 || p->prec > TFLBM_FP16S) return TFLBM_EINVAL;
-  // one row of records is addressed through a 32-bit buffer range
+  // one row of records is addressed through a 32-bit buffer range, and every
+  // row (population, capture and adjoint records) ends below the offset the
+  // kernels' dropped stores aim at (kDropBytes)
   const int64_t nblk = ((int64_t)p->nx + record_sites(p->prec) - 1) / record_sites(p->prec);
-  if (nblk * record_bytes(p->prec) >= ((int64_t)1 << 31)) return TFLBM_EINVAL;
+  const int64_t astrips = ((int64_t)p->nx + adj_record_columns() - 1) / adj_record_columns();
+  if (nblk * record_bytes(p->prec) >= kDropBytes || nblk * capture_record_bytes(p->prec) >= kDropBytes ||
+      astrips * adj_record_bytes_max(p->prec) >= kDropBytes)
+    return TFLBM_EINVAL;
   if (p->n_exp < 1 || p->n_exp > 32 || p->m_exp < 1 || p->m_exp > 32 || p->n_exp == p->m_exp) return TFLBM_EINVAL;
   if (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24) return TFLBM_EINVAL;
   if (p->gamma_field != 0 && p->gamma_field != 1) return TFLBM_EINVAL;

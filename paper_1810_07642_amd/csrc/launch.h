@@ -7,6 +7,12 @@
 
 namespace tflbm {
 
+// The buffer offset at which the kernels aim the stores they drop (halo lanes
+// and rows without output: the buffer range check discards them).  Every row
+// of every buffer (population, capture and adjoint records) must end below it,
+// which tflbm_check_params enforces.
+constexpr int kDropBytes = 0x7fff0000;
+
 // Sites per population record (= output columns of one marching strip) and
 // bytes per record, for a storage form.
 int record_sites(int prec);
@@ -42,6 +48,9 @@ hipError_t launch_adj_step(int prec, const AdjArgs &B, bool kfield, int ns, bool
 hipError_t launch_adj_finish(int prec, const AdjArgs &B, const double *h0, const double *theta, double theta0,
                              double kconst, double *grad_h0, double *grad_theta, bool w1, hipStream_t s);
 int adj_record_columns();
+// Bytes per strip of the largest adjoint row (records of either kind, or
+// the dLoss/dkappa records) for a storage form.
+int adj_record_bytes_max(int prec);
 int adj_blocks_per_cu(int prec, bool kfield, int ns, bool w1);
 
 }  // namespace tflbm

@@ -491,9 +491,9 @@ __device__ __forceinline__ unsigned int enc16x2(float a, float b, float qscale) 
   return __builtin_bit_cast(unsigned int, w);
 }
 
-// A buffer offset past every row: an access there is dropped by the buffer
-// range check and touches no memory.
-constexpr int kStoreDrop = 0x7fff0000;
+// A buffer offset past every row (kDropBytes): an access there is dropped by
+// the buffer range check and touches no memory.
+constexpr int kStoreDrop = kDropBytes;
 
 // Uniform stores.  The counter a wavefront waits on for its loads also counts
 // its stores and retires both in issue order, and the compiler sizes each

@@ -64,6 +64,32 @@ def test_too_large_lattice_rejected(lib):
     assert lib.tflbm_check_params(ctypes.byref(p)) == _lib.TFLBM_EINVAL
 
 
+# bytes per 54-column strip of the largest adjoint row (the records of nine
+# populations: FP64 for the FP64 form, FP32 for the others)
+ADJ_ROW_MAX = {0: 3968, 1: 2176, 2: 2176}
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_rows_end_below_the_dropped_store_offset(lib, prec):
+    """The kernels aim the stores they drop (halo lanes, rows without output)
+    at byte offset 0x7fff0000 of a row's buffer range, so every row must end
+    below it.  The widest accepted lattice has its population and adjoint rows
+    below the offset, one more column is rejected, although every row would
+    still fit a 32-bit range; the population rows bind in FP64, the adjoint
+    rows in FP32 and FP16S."""
+    sites, rb = RECORDS[prec]
+    lim = 0x7fff0000
+    by_records = (lim - 1) // rb * sites
+    by_adjoint = (lim - 1) // ADJ_ROW_MAX[prec] * 54
+    nx = min(by_records, by_adjoint)
+    assert (by_records < by_adjoint) == (prec == 0)
+    accept = params(lib, prec=prec, nx=nx, ny=1)
+    assert lib.tflbm_check_params(ctypes.byref(accept)) == _lib.TFLBM_OK
+    reject = params(lib, prec=prec, nx=nx + 1, ny=1)
+    assert (-(-(nx + 1) // sites)) * rb < 1 << 31
+    assert lib.tflbm_check_params(ctypes.byref(reject)) == _lib.TFLBM_EINVAL
+
+
 def test_friction_stability_warning(lib):
     # 2 nu / delta^2 >= 2: nu = 1/6 needs delta > sqrt(1/6) ~ 0.408
     p = params(lib, delta=0.3)
