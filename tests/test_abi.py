@@ -90,6 +90,18 @@ def test_rows_end_below_the_dropped_store_offset(lib, prec):
     assert lib.tflbm_check_params(ctypes.byref(reject)) == _lib.TFLBM_EINVAL
 
 
+def test_steps_per_pass_needs_an_initialised_handle(lib):
+    """tflbm_steps_per_pass: EINVAL for NULL, ESTATE before tflbm_init (the
+    plan is fixed at init, from the device's occupancy)."""
+    assert lib.tflbm_steps_per_pass(None) == _lib.TFLBM_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.tflbm_create(ctypes.byref(params(lib)), ctypes.byref(h)) == _lib.TFLBM_OK
+    try:
+        assert lib.tflbm_steps_per_pass(h) == _lib.TFLBM_ESTATE
+    finally:
+        lib.tflbm_destroy(h)
+
+
 def test_friction_stability_warning(lib):
     # 2 nu / delta^2 >= 2: nu = 1/6 needs delta > sqrt(1/6) ~ 0.408
     p = params(lib, delta=0.3)
