@@ -22,7 +22,7 @@ struct tflbm_sim {
   int64_t steps = 0;
   double kconst = 0.0;    // (n - 1)(m - 1)/((n - m) h_*)
   double kappa0 = 0.0;    // kappa of the uniform theta0
-  // launch shape of the forward step: one step per pass, and two fused steps
+  // launch shapes of the forward step: one, two and three fused steps per pass
   int nstrips = 0, rows = 0, ntiles = 0, per_xcd = 0;
   int rows2 = 0, ntiles2 = 0, per_xcd2 = 0;
   int rows3 = 0, ntiles3 = 0, per_xcd3 = 0;

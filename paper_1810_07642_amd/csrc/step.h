@@ -14,18 +14,20 @@
 // store of a wavefront covers whole 128-byte lines of a record.
 //
 // Step kernel: one wavefront owns one record column (B output columns) plus a
-// halo of (64 V - B)/2 = 6 columns per side, and a chunk of H rows, and
-// marches down the rows.  Per row it reads the nine segments of the row's
-// records (coalesced, prefetched two rows ahead), assembles the deviations of
-// its own columns (x shift through a cross-lane move), forms dh; one row later
-// the film pressure of the previous row (Laplacian and disjoining term), kept
-// as its x difference and x-smoothed value; one more row later the isotropic
-// pressure gradient, forces, equilibrium and collision of the row two above,
-// whose populations were parked in LDS, and stores them.  Stencil neighbours
-// in x come from adjacent lanes; no barriers.  With two fused steps a second
-// such stage consumes the first one's output rows in registers, so every
-// record crosses HBM once per two steps; the halo columns and the ten halo
-// rows of a chunk are re-read (partly from L2).
+// halo of (64 V - B)/2 columns per side (9 FP64, 10 FP32, 6 FP16S: three per
+// fused step), and a chunk of H rows, and marches down the rows.  Per row it
+// reads the nine segments of the row's records (coalesced, prefetched one to
+// three rows ahead), assembles the deviations of its own columns (x shift
+// through a cross-lane move), forms dh; one row later the film pressure of
+// the previous row (Laplacian and disjoining term), kept as its x difference
+// and x-smoothed value; one more row later the isotropic pressure gradient,
+// forces, equilibrium and collision of the row two above, whose populations
+// (or, with omega = 1, only their j) wait in LDS, and stores them.  Stencil
+// neighbours in x come from adjacent lanes; no barriers.  With NS fused steps
+// (two, or three with omega = 1) further such stages consume the previous
+// one's output rows in registers, so every record crosses HBM once per NS
+// steps; the halo columns and the 2 (2 + 3 (NS - 1)) halo rows of a chunk are
+// re-read (partly from L2).
 #pragma once
 
 #include <type_traits>
@@ -914,9 +916,11 @@ __global__ __launch_bounds__(64, 2) void step_kernel(StepArgs A) {
   constexpr int KST = 4 + 6 * (NS - 1);
   auto rsrc_src = [&](int row) { return make_rsrc(A.src + row * rowB, (uint32_t)rowB); };
   int ry = wrap(y0 - HALO, ny);                          // row r of stage 0
-  // rows are loaded PF rows ahead of their use.  Measured at 4096^2 (MLUPS,
-  // two rows ahead / three): FP16S 142.8k / 146.9k (its decoding makes each
-  // row wait longer for its loads), FP32 113.9k / 113.3k, FP64 57.9k / 58.0k.
+  // rows are loaded PF rows ahead of their use.  Measured at 4096^2 with two
+  // fused steps (MLUPS, two rows ahead / three): FP16S 142.8k / 146.9k (its
+  // decoding makes each row wait longer for its loads), FP32 113.9k / 113.3k,
+  // FP64 57.9k / 58.0k.  The three-step kernels load one row ahead: two would
+  // need more than 256 VGPRs.
   constexpr int PF = P == kF16S ? 3 : (NS == 3 ? 1 : 2);
   int rpre = (ry + PF) % ny;                             // row r + PF
   // FP16S decodes row r with rows r - 1 and r + 1 (fp16s_decode): the row
