@@ -541,7 +541,7 @@ __global__ __launch_bounds__(64) void adj_step_kernel(AdjArgs A) {
 // kAdjW columns plus five halo columns per side (two per stage plus the
 // one-column shift between them); rows y0-5 .. yend+4 are read (W1: the
 // fields of rows y0-6 .. yend+5).
-template <typename T, bool KF, bool W1 = false>
+template <typename T, bool KF, bool W1 = false, bool LONG = false>
 __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
   __shared__ T ring[5][9][64];
   __shared__ double gring[4][64];
@@ -679,14 +679,37 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
   // each history value in place instead of moving it along every row (a
   // quarter of the loop's VALU instructions were such moves with pairs):
   // 4096^2 FP32 with omega = 1 186 -> 174 us per step, 1024^2 20.0 -> 17.7
+  // LONG (chunks of at least kAdjLongRows rows): the ten rows before the first
+  // output row, then groups in which the compiler is told that every row
+  // outputs and loads two rows ahead, so a group is straight-line code whose
+  // waits leave the younger loads and stores in flight (4096^2 FP32 157.9 ->
+  // 149.0 us per step, bitwise the same); on short chunks, where most rows
+  // fall outside such groups, this loses (1024^2 16.5 -> 17.5 us) and the
+  // kernel keeps the plain groups
   int k = 0;
-  for (; k + 5 < K; k += 6) {
-    iteration(k, ia, ca, gka, gkb);
-    iteration(k + 1, ib, cb, gkb, gka);
-    iteration(k + 2, ia, ca, gka, gkb);
-    iteration(k + 3, ib, cb, gkb, gka);
-    iteration(k + 4, ia, ca, gka, gkb);
-    iteration(k + 5, ib, cb, gkb, gka);
+  if constexpr (LONG) {
+    for (; k < 10; k += 2) {  // K > 10: a chunk has at least one row
+      iteration(k, ia, ca, gka, gkb);
+      iteration(k + 1, ib, cb, gkb, gka);
+    }
+    for (; k + 7 < K; k += 6) {
+      __builtin_assume(k >= 10 && k + 7 < K);
+      iteration(k, ia, ca, gka, gkb);
+      iteration(k + 1, ib, cb, gkb, gka);
+      iteration(k + 2, ia, ca, gka, gkb);
+      iteration(k + 3, ib, cb, gkb, gka);
+      iteration(k + 4, ia, ca, gka, gkb);
+      iteration(k + 5, ib, cb, gkb, gka);
+    }
+  } else {
+    for (; k + 5 < K; k += 6) {
+      iteration(k, ia, ca, gka, gkb);
+      iteration(k + 1, ib, cb, gkb, gka);
+      iteration(k + 2, ia, ca, gka, gkb);
+      iteration(k + 3, ib, cb, gkb, gka);
+      iteration(k + 4, ia, ca, gka, gkb);
+      iteration(k + 5, ib, cb, gkb, gka);
+    }
   }
   for (; k + 1 < K; k += 2) {
     iteration(k, ia, ca, gka, gkb);
@@ -762,12 +785,21 @@ __global__ void adj_finish_kernel(AdjArgs A, const double *h0, const double *the
   }
 }
 
+// Chunks from which the two-step reverse kernel takes its LONG row loop.
+constexpr int kAdjLongRows = 32;
+
 template <typename T, bool W1>
 static hipError_t adj_step_t(const AdjArgs &B, bool kf, int ns, hipStream_t s) {
   const dim3 grid(8 * B.per_xcd), block(64);
   if (ns == 2) {
-    if (kf) adj_step2_kernel<T, true, W1><<<grid, block, 0, s>>>(B);
-    else adj_step2_kernel<T, false, W1><<<grid, block, 0, s>>>(B);
+    const bool lng = B.H >= kAdjLongRows;
+    if (kf) {
+      if (lng) adj_step2_kernel<T, true, W1, true><<<grid, block, 0, s>>>(B);
+      else adj_step2_kernel<T, true, W1><<<grid, block, 0, s>>>(B);
+    } else {
+      if (lng) adj_step2_kernel<T, false, W1, true><<<grid, block, 0, s>>>(B);
+      else adj_step2_kernel<T, false, W1><<<grid, block, 0, s>>>(B);
+    }
   } else {
     if (kf) adj_step_kernel<T, true, W1><<<grid, block, 0, s>>>(B);
     else adj_step_kernel<T, false, W1><<<grid, block, 0, s>>>(B);

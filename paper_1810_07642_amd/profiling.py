@@ -55,7 +55,7 @@ PROFILE_STEPS = 24  # a multiple of 2 and of 3: whole passes of the kernel
 # kappa 4 + g_kappa 8 read; fields 12 + g_kappa 8 written.  (The general pass
 # moves nine adjoint populations: 72 read, 44 written.)
 ADJ_BYTES = (48, 20)
-ADJ_KERNEL = "adj_step2_kernel<float, true, true>"
+ADJ_KERNEL = "adj_step2_kernel<float, true, true, true>"
 CALIB_BYTES = 1 << 30  # the 1 GiB calibration copy
 CLOCK_GHZ = 2.4
 SIMDS = 256 * 4

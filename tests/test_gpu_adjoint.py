@@ -229,6 +229,7 @@ def _reverse_pass(prec, h0, th, p, nsteps, grad_h, fused, field):
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
 @pytest.mark.parametrize("shape,rows2,field,nsteps", [
     ((150, 173), "7", True, 7),      # four strips (the last 11 columns), 22 row chunks, the last of 3 rows
+    ((150, 173), "40", True, 7),     # chunks of 40 rows (the long-chunk row loop), the last of 30
     ((45, 70), None, False, 6),      # uniform kappa, an even number of steps
     ((3, 2), None, True, 5),         # every row and column wraps onto the others
 ])
@@ -260,6 +261,7 @@ def test_two_steps_per_pass_equal_single_steps_bitwise(prec, shape, rows2, field
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
 @pytest.mark.parametrize("shape,rows2,field,nsteps", [
     ((150, 173), "7", True, 7),
+    ((150, 173), "40", True, 7),
     ((45, 70), None, False, 6),
     ((3, 2), None, True, 5),
     ((64, 131), None, True, 9),
