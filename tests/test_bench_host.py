@@ -52,6 +52,18 @@ def test_committed_adjoint_summary_matches_the_sources():
     assert val[1] == 2 and alg <= val[0] <= 1.5 * alg
 
 
+def test_headline_mean_leaves_out_the_shorter_lattices():
+    """The bench also steps smaller lattices whose launches share the 4096^2
+    launches' kernel and grid; the launch mean of a summary keeps the majority,
+    the launches within a factor of two of the median, and says how many it
+    left out."""
+    d = [600.0e3] * 100 + [64.0e3] * 10 + [185.0e3] * 5
+    mean, left = profiling.headline_mean(d)
+    assert left == 15 and mean == 600.0e3
+    mean, left = profiling.headline_mean([590.0, 610.0, 600.0])
+    assert left == 0 and abs(mean - 600.0) < 1e-9
+
+
 def test_roofline_block_is_a_fraction_of_the_peak():
     # 152 B x 4096^2 per launch in 0.6 ms: 4.25 TB/s, 0.53 of 8 TB/s
     blk = bench.roofline_block("k", 152 * 4096 * 4096, 0.6, (1.1 * 152 * 4096 * 4096, 2), 5000.0)
