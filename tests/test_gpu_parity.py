@@ -56,7 +56,14 @@ def test_fp64_uniform_theta_path_matches_oracle():
 
 def test_fp64_sessile_drop_2000_steps():
     """The relaxing drop (64 x 64, cap r = 20 apex 8 on h_* = 0.05, theta =
-    pi/9), 2000 steps, FP64: h and u against the oracle, mass drift."""
+    pi/9), 2000 steps, FP64: h and u against the oracle, mass drift, and the
+    configuration's angle check.  At h_* = 0.05 the precursor-to-drop
+    transition, h_*/tan(theta) = 0.14 lattice units, is narrower than a site
+    and the lattice pins the contact line: the apparent angle falls from
+    43.5 deg only to 39.1 deg, not to theta = 20 deg, on the GPU as in the
+    oracle (the thick-precursor drops of
+    test_relaxed_drop_contact_angle_all_forms relax to theta)."""
+    from physics import contact_angle
     banner("fp64 sessile drop 64x64 x 2000")
     p, h0, th = inputs.sessile_drop()
     ho, uxo, uyo, mo = oracle_run(p, h0, th, 2000)
@@ -66,6 +73,11 @@ def test_fp64_sessile_drop_2000_steps():
     assert max_rel(uyg, uyo) <= 100 * TOL64
     m0 = float(h0.sum())
     assert abs(mg - m0) <= 1e-13 * m0
+    a0, ao, ag = (contact_angle(h.numpy(), p["hstar"]) for h in (h0, ho, hg))
+    print(f"contact angle {math.degrees(a0):.3f} -> {math.degrees(ag):.3f} deg (oracle "
+          f"{math.degrees(ao):.3f}), theta {math.degrees(th[0, 0].item()):.1f}")
+    assert abs(ag - ao) <= 1e-9 * ao
+    assert ag < a0 and ag > 1.8 * th[0, 0].item()
 
 
 @pytest.mark.parametrize("case", [0, 1, 2, 5])
