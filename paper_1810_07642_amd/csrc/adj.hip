@@ -693,6 +693,16 @@ __global__ __launch_bounds__(64) void adj_step2_kernel(AdjArgs A) {
       iteration(k + 1, ib, cb, gkb, gka);
     }
     for (; k + 7 < K; k += 6) {
+      // k is the same in every lane.  Stated here, before the range, it keeps
+      // the row arithmetic and the buffer resources scalar in the rows after
+      // the groups too: without it the compiler took k as per-lane in the
+      // two-row loop below and wrapped each of its row loads and stores in a
+      // loop over the lanes' resources (four readfirstlanes, two 64-bit
+      // compares and an exec-mask branch each; 1 % of the VALU instructions
+      // at 4096^2, no change in time).  Stated inside `iteration` instead, it
+      // hides the range from the stage tests, which then branch
+      // (4096^2 149 -> 166 us per step).
+      k = __builtin_amdgcn_readfirstlane(k);
       __builtin_assume(k >= 10 && k + 7 < K);
       iteration(k, ia, ca, gka, gkb);
       iteration(k + 1, ib, cb, gkb, gka);
