@@ -29,6 +29,7 @@ struct tflbm_sim {
   int fuse = 0;           // most steps per pass: 1, 2 or 3; 0 = by lattice size (fuse3_fits, fuse_fits)
   bool fuse_fits = false; // the lattice is too large for one round of one-row tiles
   bool fuse3_fits = false;  // three steps per pass (omega = 1) beat two on this lattice
+  bool rem2_general = false;  // FP64, omega = 1, three steps per pass: two-step passes run the general stages
   bool w1 = false;        // omega = 1 (tau = 1): the stages without a population history
   // launch-bound lattices: blocks of steps replayed from captured graphs, one
   // per starting buffer parity, captured on a stream of the library's own

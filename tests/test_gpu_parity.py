@@ -383,6 +383,40 @@ def test_omega1_stages_equal_general_stages_bitwise(prec, g):
                     assert torch.equal(a, b), (prec, g, ny, nx, field)
 
 
+def test_fp64_two_step_remainder_on_three_step_lattice_bitwise():
+    """FP64 at tau = 1 on a lattice that runs three steps per pass: a call of
+    5 or 8 steps ends on a two-step pass, which runs the general stages'
+    two-step kernel there.  The same bits as omega = 1 single steps and as the
+    general stages throughout (TFLBM_OMEGA1=0), for a theta field and uniform
+    theta."""
+    import os
+    from paper_1810_07642_amd import Sim
+    p = dict(tau=1.0, gamma=0.01, g=1e-3, hstar=0.1, delta=1.0, ax=1e-5, ay=-1e-5)
+    ny = nx = 1024
+    h0, th = random_case(ny, nx, 47)
+    for field in ("theta", "uniform"):
+        for nsteps in (5, 8):
+            banner(f"fp64 two-step remainder: {ny}x{nx} {field} {nsteps} steps")
+            runs = []
+            for env in ({}, {"TFLBM_FUSE": "1"}, {"TFLBM_OMEGA1": "0"}):
+                os.environ.update(env)
+                try:
+                    sim = Sim(nx, ny, "fp64", **p)
+                finally:
+                    for k in env:
+                        del os.environ[k]
+                sim.init(h0, None if field == "uniform" else th)
+                if not env:
+                    assert sim.steps_per_pass == 3
+                sim.step(nsteps)
+                sim.check()
+                runs.append((sim.state_save().cpu(),) + tuple(t.cpu() for t in sim.read()))
+                del sim
+            for other in runs[1:]:
+                for a, b in zip(other, runs[0]):
+                    assert torch.equal(a, b), (field, nsteps)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16s"])
 def test_graph_replayed_steps_equal_launched_steps_bitwise(prec):
     """On launch-bound lattices tflbm_step sends whole blocks of 64 steps as
